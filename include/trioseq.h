@@ -1,0 +1,175 @@
+/*
+ * trioseq.h -- C ABI of libtrioseq: exact global 3-way (triplet) alignment
+ * scoring of DNA on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper, Section II, Eq. 1, sum-of-pairs definition and the
+ * "Global Alignments" initialisation): for sequences S0, S1, S2 of lengths
+ * a, b, c, the optimal global sum-of-pairs score is M[a][b][c] of the tensor
+ *   M[i][j][k] = max over the 7 moves that consume a non-empty subset of the
+ *                next residues of S0, S1, S2, of  M[predecessor] + SOP(column),
+ *   SOP(x,y,z) = s(x,y) + s(x,z) + s(y,z),  s(r,r') = sub[r][r'],
+ *   s(r,-) = s(-,r) = gap,  s(-,-) = 0,  M[0][0][0] = 0,
+ * which equals the best summed column score over all 3-row global alignments.
+ * Scores are exact int32; there is no tolerance.
+ *
+ * Conventions for every call:
+ *  - Residues are A, C, G, T (either case) with codes 0, 1, 2, 3. Anything
+ *    else is rejected with TRIOSEQ_ERR_BAD_RESIDUE.
+ *  - Packed form: 16 residues per uint32, residue p of a sequence at bits
+ *    2*(p % 16) .. 2*(p % 16)+1 of word p / 16 (trioseq_pack).
+ *  - Lengths may be 0. A triplet's cell count is a*b*c (the paper's TCUPS
+ *    definition, Section V-A).
+ *  - Every call returns a trioseq_status; on error the outputs are left
+ *    untouched, no kernel has been launched, and trioseq_last_error() returns
+ *    a message for the calling thread. Batch validation is all-or-nothing and
+ *    the message names the first bad triplet.
+ *  - No C++ exception crosses this ABI.
+ *  - "hip_stream" arguments take a hipStream_t (NULL = the null stream).
+ */
+#ifndef TRIOSEQ_H
+#define TRIOSEQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum trioseq_status {
+  TRIOSEQ_OK = 0,
+  TRIOSEQ_ERR_INVALID_ARG = -1, /* null pointer, asymmetric matrix, bad option */
+  TRIOSEQ_ERR_BAD_RESIDUE = -2, /* a character outside ACGTacgt */
+  TRIOSEQ_ERR_TOO_LARGE = -3,   /* lengths beyond what the kernels support */
+  TRIOSEQ_ERR_OVERFLOW = -4,    /* the score range could exceed int32 headroom */
+  TRIOSEQ_ERR_NOMEM = -5,       /* host or device allocation failed */
+  TRIOSEQ_ERR_DEVICE = -6,      /* a HIP call failed; message has the HIP error */
+  TRIOSEQ_ERR_BUSY = -7,        /* server queue full; retry later */
+  TRIOSEQ_ERR_TIMEOUT = -8,     /* wait ended before the result was ready */
+  TRIOSEQ_ERR_CLOSED = -9       /* server is shutting down */
+} trioseq_status;
+
+/* Scoring scheme (Section II: sigma and the linear gap value alpha).
+ * sub must be symmetric (the sum-of-pairs score treats the three sequences
+ * alike). gap is the score of one residue against a gap (normally negative);
+ * gap against gap always scores 0. Limits: every sub[x][y] - 2*gap lies in
+ * [-127, 127] (the kernels keep these terms as bytes). */
+typedef struct trioseq_scoring {
+  int32_t sub[4][4];
+  int32_t gap;
+} trioseq_scoring;
+
+/* Fills sub with match on the diagonal and mismatch elsewhere. */
+void trioseq_scoring_simple(trioseq_scoring* s, int32_t match, int32_t mismatch, int32_t gap);
+
+/* One triplet as host ASCII. seq[s] may be NULL only if len[s] == 0. */
+typedef struct trioseq_triplet {
+  const char* seq[3];
+  uint32_t len[3];
+} trioseq_triplet;
+
+/* Host helpers (no device work). */
+/* Packs len ASCII residues into ceil(len/16) words (caller-owned). */
+trioseq_status trioseq_pack(const char* seq, uint32_t len, uint32_t* words);
+/* Default packed layout for n triplets: every sequence starts on a fresh
+ * word, triplet-major. Writes 3n word offsets and the total word count. */
+trioseq_status trioseq_packed_layout(const uint32_t* lens, size_t n, uint64_t* word_off,
+                                     uint64_t* total_words);
+
+/* Score of one triplet; synchronous. score is a host int32. */
+trioseq_status trioseq_score(const trioseq_triplet* t, const trioseq_scoring* sc, int32_t* score);
+
+/* Scores of n triplets, computed together (one persistent launch for the
+ * batch). Synchronous: returns when scores[0..n) (host memory) are written.
+ * Work is issued on hip_stream. */
+trioseq_status trioseq_score_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
+                                   int32_t* scores, void* hip_stream);
+
+/* ---- Plans: device-resident batches (inputs already in HBM). ---------- */
+
+typedef struct trioseq_plan trioseq_plan;
+
+typedef struct trioseq_plan_options {
+  int32_t engine;    /* -1 auto; 0 = batch (one wavefront per triplet, persistent
+                        queue); 1 = wide (one triplet over many wavefronts) */
+  int32_t tile_rows; /* lane tile rows; 0 = automatic (tuned table or default) */
+  int32_t tile_cols; /* lane tile columns; 0 = automatic */
+  int32_t grid;      /* wavefronts to launch; 0 = fill the device */
+  int32_t use_graph; /* 1 = capture the launch sequence in a hipGraph and replay it */
+} trioseq_plan_options;
+
+typedef struct trioseq_plan_info {
+  int32_t engine, tile_rows, tile_cols, grid, waves_per_cu, panels;
+  uint64_t workspace_bytes;
+  double cells; /* sum of a*b*c over the batch */
+} trioseq_plan_info;
+
+/* Plans scores for n triplets whose lengths are lens[3t+s] (host array) and
+ * whose packed words will live at word offsets word_off[3t+s] (host array;
+ * NULL = trioseq_packed_layout). opts may be NULL. Allocates the device
+ * workspace on the current HIP device; the plan owns it. */
+trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_off, size_t n,
+                                   const trioseq_scoring* sc, const trioseq_plan_options* opts,
+                                   trioseq_plan** plan);
+/* Enqueues the scoring of the planned batch on hip_stream. d_words: packed
+ * residues in device memory; d_scores: n int32 in device memory (score of
+ * triplet t at d_scores[t]). Asynchronous: both buffers must stay alive until
+ * the stream passes this point. Runs of one plan must not overlap in time
+ * (they share the plan's workspace). */
+trioseq_status trioseq_plan_run(trioseq_plan* plan, const uint32_t* d_words, int32_t* d_scores,
+                                void* hip_stream);
+trioseq_status trioseq_plan_get_info(const trioseq_plan* plan, trioseq_plan_info* info);
+trioseq_status trioseq_plan_destroy(trioseq_plan* plan);
+
+/* ---- Serving: continuous batching of a request stream. ---------------- */
+
+typedef struct trioseq_server trioseq_server;
+
+typedef struct trioseq_serve_config {
+  int32_t device;            /* HIP device ordinal */
+  uint64_t max_device_bytes; /* admission budget for workspaces (0 = 1/4 of HBM) */
+  uint32_t max_len;          /* longest accepted sequence */
+  uint32_t max_queue;        /* pending requests before submit returns BUSY */
+  uint32_t max_batch;        /* triplets per device round (0 = automatic) */
+} trioseq_serve_config;
+
+typedef struct trioseq_result {
+  uint64_t id;
+  int32_t score;
+  int32_t status;         /* trioseq_status of this request */
+  uint64_t t_submit_ns;   /* steady clock at submit */
+  uint64_t t_done_ns;     /* steady clock when the score reached the host */
+} trioseq_result;
+
+typedef struct trioseq_serve_stats {
+  uint64_t submitted, completed, failed, rounds;
+  double cells;           /* sum of a*b*c over completed requests */
+  double busy_s;          /* wall time with at least one round in flight */
+  double p50_ns, p99_ns;  /* submit-to-result latency over completed requests */
+} trioseq_serve_stats;
+
+trioseq_status trioseq_serve_create(const trioseq_serve_config* cfg, const trioseq_scoring* sc,
+                                    trioseq_server** srv);
+/* Copies the triplet; never blocks on the device. BUSY when the queue is full. */
+trioseq_status trioseq_serve_submit(trioseq_server* srv, const trioseq_triplet* t, uint64_t* id);
+/* Moves up to cap finished results into out; never blocks. */
+trioseq_status trioseq_serve_poll(trioseq_server* srv, trioseq_result* out, size_t cap,
+                                  size_t* n_out);
+/* Blocks until request id finishes (or timeout_ns passes; <0 = forever). The
+ * result is consumed: it will not be returned by poll. */
+trioseq_status trioseq_serve_wait(trioseq_server* srv, uint64_t id, trioseq_result* out,
+                                  int64_t timeout_ns);
+trioseq_status trioseq_serve_get_stats(trioseq_server* srv, trioseq_serve_stats* st);
+/* Stops admission, finishes queued and in-flight work, frees everything. */
+trioseq_status trioseq_serve_destroy(trioseq_server* srv);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* trioseq_last_error(void);
+
+/* Library version string. */
+const char* trioseq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRIOSEQ_H */

@@ -1,0 +1,281 @@
+"""Python binding of libtrioseq (exact global 3-way alignment scores on MI355X).
+
+Argument marshalling only: every step of the scoring path runs in the HIP
+library (``libtrioseq.so``, built by ``build.py``). If the library is not
+built, importing the binding's functions raises; there is no CPU fallback.
+PyTorch is used only to own device buffers and to name HIP streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtrioseq.so")
+
+OK = 0
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BAD_RESIDUE", -3: "TOO_LARGE", -4: "OVERFLOW",
+          -5: "NOMEM", -6: "DEVICE", -7: "BUSY", -8: "TIMEOUT", -9: "CLOSED"}
+
+
+class TrioseqError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class Scoring(ctypes.Structure):
+    _fields_ = [("sub", (ctypes.c_int32 * 4) * 4), ("gap", ctypes.c_int32)]
+
+
+class Triplet(ctypes.Structure):
+    _fields_ = [("seq", ctypes.c_char_p * 3), ("len", ctypes.c_uint32 * 3)]
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("engine", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("tile_cols", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("engine", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("tile_cols", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("panels", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_uint64), ("cells", ctypes.c_double)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_device_bytes", ctypes.c_uint64),
+                ("max_len", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("score", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("t_submit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("cells", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("p50_ns", ctypes.c_double), ("p99_ns", ctypes.c_double)]
+
+
+# Every symbol the C header declares (checked by the CPU test-suite).
+EXPORTS = [
+    "trioseq_scoring_simple", "trioseq_pack", "trioseq_packed_layout", "trioseq_score",
+    "trioseq_score_batch", "trioseq_plan_create", "trioseq_plan_run", "trioseq_plan_get_info",
+    "trioseq_plan_destroy", "trioseq_serve_create", "trioseq_serve_submit", "trioseq_serve_poll",
+    "trioseq_serve_wait", "trioseq_serve_get_stats", "trioseq_serve_destroy",
+    "trioseq_last_error", "trioseq_version",
+]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_2605_28400_amd/build.py (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    st = ctypes.c_int
+    L.trioseq_scoring_simple.argtypes = [P(Scoring), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.trioseq_scoring_simple.restype = None
+    L.trioseq_pack.argtypes = [ctypes.c_char_p, ctypes.c_uint32, P(ctypes.c_uint32)]
+    L.trioseq_pack.restype = st
+    L.trioseq_packed_layout.argtypes = [P(ctypes.c_uint32), ctypes.c_size_t, P(ctypes.c_uint64),
+                                        P(ctypes.c_uint64)]
+    L.trioseq_packed_layout.restype = st
+    L.trioseq_score.argtypes = [P(Triplet), P(Scoring), P(ctypes.c_int32)]
+    L.trioseq_score.restype = st
+    L.trioseq_score_batch.argtypes = [P(Triplet), ctypes.c_size_t, P(Scoring), P(ctypes.c_int32),
+                                      ctypes.c_void_p]
+    L.trioseq_score_batch.restype = st
+    L.trioseq_plan_create.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint64), ctypes.c_size_t,
+                                      P(Scoring), P(PlanOptions), P(ctypes.c_void_p)]
+    L.trioseq_plan_create.restype = st
+    L.trioseq_plan_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.trioseq_plan_run.restype = st
+    L.trioseq_plan_get_info.argtypes = [ctypes.c_void_p, P(PlanInfo)]
+    L.trioseq_plan_get_info.restype = st
+    L.trioseq_plan_destroy.argtypes = [ctypes.c_void_p]
+    L.trioseq_plan_destroy.restype = st
+    L.trioseq_serve_create.argtypes = [P(ServeConfig), P(Scoring), P(ctypes.c_void_p)]
+    L.trioseq_serve_create.restype = st
+    L.trioseq_serve_submit.argtypes = [ctypes.c_void_p, P(Triplet), P(ctypes.c_uint64)]
+    L.trioseq_serve_submit.restype = st
+    L.trioseq_serve_poll.argtypes = [ctypes.c_void_p, P(Result), ctypes.c_size_t, P(ctypes.c_size_t)]
+    L.trioseq_serve_poll.restype = st
+    L.trioseq_serve_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, P(Result), ctypes.c_int64]
+    L.trioseq_serve_wait.restype = st
+    L.trioseq_serve_get_stats.argtypes = [ctypes.c_void_p, P(ServeStats)]
+    L.trioseq_serve_get_stats.restype = st
+    L.trioseq_serve_destroy.argtypes = [ctypes.c_void_p]
+    L.trioseq_serve_destroy.restype = st
+    L.trioseq_last_error.argtypes = []
+    L.trioseq_last_error.restype = ctypes.c_char_p
+    L.trioseq_version.argtypes = []
+    L.trioseq_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != OK:
+        raise TrioseqError(status, lib().trioseq_last_error().decode(errors="replace"))
+
+
+def scoring(match: int = 1, mismatch: int = -1, gap: int = -2, sub=None) -> Scoring:
+    """Scoring scheme; ``sub`` (4x4) overrides match/mismatch."""
+    s = Scoring()
+    if sub is None:
+        lib().trioseq_scoring_simple(ctypes.byref(s), match, mismatch, gap)
+    else:
+        sub = np.asarray(sub, dtype=np.int64)
+        for x in range(4):
+            for y in range(4):
+                s.sub[x][y] = int(sub[x][y])
+        s.gap = int(gap)
+    return s
+
+
+DEFAULT = None
+
+
+def _default_scoring() -> Scoring:
+    global DEFAULT
+    if DEFAULT is None:
+        DEFAULT = scoring()
+    return DEFAULT
+
+
+def _as_bytes(seq) -> bytes:
+    if isinstance(seq, (bytes, bytearray)):
+        return bytes(seq)
+    if isinstance(seq, str):
+        return seq.encode()
+    arr = np.asarray(seq, dtype=np.uint8)
+    return np.frombuffer(b"ACGT", dtype=np.uint8)[arr].tobytes()
+
+
+def _triplet(t, keep: list) -> Triplet:
+    tr = Triplet()
+    for s in range(3):
+        b = _as_bytes(t[s])
+        keep.append(b)
+        tr.seq[s] = b
+        tr.len[s] = len(b)
+    return tr
+
+
+def score(triplet, sc: Scoring | None = None) -> int:
+    """Exact global SOP score of one triplet (ASCII strings/bytes or code arrays)."""
+    keep: list = []
+    tr = _triplet(triplet, keep)
+    out = ctypes.c_int32()
+    check(lib().trioseq_score(ctypes.byref(tr), ctypes.byref(sc or _default_scoring()), ctypes.byref(out)))
+    return int(out.value)
+
+
+def score_batch(triplets, sc: Scoring | None = None, stream=None) -> np.ndarray:
+    """Scores of many triplets in one persistent launch (synchronous)."""
+    keep: list = []
+    n = len(triplets)
+    arr = (Triplet * max(n, 1))()
+    for q, t in enumerate(triplets):
+        arr[q] = _triplet(t, keep)
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    check(lib().trioseq_score_batch(arr, n, ctypes.byref(sc or _default_scoring()),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    _stream_ptr(stream)))
+    return out[:n]
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+def pack(seq) -> np.ndarray:
+    """2-bit packed words of one sequence (16 residues per uint32)."""
+    b = _as_bytes(seq)
+    words = np.zeros(max((len(b) + 15) // 16, 1), dtype=np.uint32)
+    check(lib().trioseq_pack(b, len(b), words.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return words[:(len(b) + 15) // 16]
+
+
+def pack_batch(triplets):
+    """(lens[3n] uint32, word_off[3n] uint64, words uint32) in the default layout."""
+    n = len(triplets)
+    lens = np.array([[len(_as_bytes(s)) if not isinstance(s, np.ndarray) else s.size for s in t]
+                     for t in triplets], dtype=np.uint32).reshape(3 * n)
+    off = np.zeros(max(3 * n, 1), dtype=np.uint64)
+    total = ctypes.c_uint64()
+    check(lib().trioseq_packed_layout(lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), n,
+                                      off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                      ctypes.byref(total)))
+    words = np.zeros(max(int(total.value), 1), dtype=np.uint32)
+    for q, t in enumerate(triplets):
+        for s in range(3):
+            w = pack(t[s])
+            o = int(off[3 * q + s])
+            words[o:o + w.size] = w
+    return lens, off[:3 * n], words
+
+
+class Plan:
+    """Device-resident batch plan: ``run`` enqueues one scoring pass on a stream."""
+
+    def __init__(self, lens, word_off=None, sc: Scoring | None = None, engine: int = -1,
+                 tile=(0, 0), grid: int = 0, use_graph: bool = False):
+        self.lens = np.ascontiguousarray(lens, dtype=np.uint32)
+        self.n = self.lens.size // 3
+        off_p = None
+        if word_off is not None:
+            self._off = np.ascontiguousarray(word_off, dtype=np.uint64)
+            off_p = self._off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        opts = PlanOptions(engine, tile[0], tile[1], grid, 1 if use_graph else 0)
+        self._h = ctypes.c_void_p()
+        check(lib().trioseq_plan_create(self.lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                        off_p, self.n, ctypes.byref(sc or _default_scoring()),
+                                        ctypes.byref(opts), ctypes.byref(self._h)))
+
+    def run(self, d_words, d_scores, stream=None) -> None:
+        """d_words / d_scores: device tensors (torch) or raw device pointers."""
+        wp = d_words.data_ptr() if hasattr(d_words, "data_ptr") else int(d_words)
+        sp = d_scores.data_ptr() if hasattr(d_scores, "data_ptr") else int(d_scores)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        check(lib().trioseq_plan_run(self._h, ctypes.c_void_p(wp), ctypes.c_void_p(sp),
+                                     _stream_ptr(stream)))
+
+    def info(self) -> dict:
+        i = PlanInfo()
+        check(lib().trioseq_plan_get_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in PlanInfo._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            lib().trioseq_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def version() -> str:
+    return lib().trioseq_version().decode()

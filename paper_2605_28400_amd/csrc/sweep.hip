@@ -1,0 +1,579 @@
+// gfx950 kernels for exact global 3-way alignment scoring.
+//
+// What is computed (paper, Section II, Eq. 1 with the global initialisation):
+// M[i][j][k] is the best of seven predecessor moves plus the sum-of-pairs
+// score of the move's column, M[0][0][0] = 0, and the answer is M[n0][n1][n2].
+//
+// Shifted recurrence. Every move adds 2*gap per consumed residue on top of
+// its substitution terms, so with M'(i,j,k) = M(i,j,k) - 2*gap*(i+j+k) the
+// seven candidates become
+//   M'(i-1,j,k), M'(i,j-1,k), M'(i,j,k-1)                  (one residue, +0)
+//   M'(i-1,j-1,k) + A, M'(i-1,j,k-1) + B, M'(i,j-1,k-1) + C (two residues)
+//   M'(i-1,j-1,k-1) + A + B + C                             (three residues)
+// with A = s(a,b) - 2*gap, B = s(a,c) - 2*gap, C = s(b,c) - 2*gap for the
+// residues a = S0[i-1], b = S1[j-1], c = S2[k-1]. This is exact integer
+// algebra (A + B + C = SOP - 6*gap), and M' >= 0 for every cell because the
+// path of single-residue moves scores exactly 0 in M'.
+//
+// Decomposition (designed for CDNA4; the paper's warp-tile kernel is prior art):
+//  * The (j,k) plane is cut into panels of (8*RJ) x (8*RK) cells. One
+//    wavefront owns a panel; its 64 lanes form an 8 x 8 grid and each lane
+//    keeps an RJ x RK tile in VGPRs.
+//  * The wavefront sweeps the whole S0 axis for its panel. Lane (y,x)
+//    processes slice i = t - y - x at step t, so its left and upper
+//    neighbours finished the same slice one step earlier. Their edge values
+//    move through a per-wave LDS slot array (LDS operations of one wave
+//    execute in order, so no barrier is needed). Panel edges come from LDS
+//    rings that are filled one chunk (8 steps) ahead from face buffers in
+//    HBM/L2, through buffer loads; faces are written with buffer stores
+//    whose out-of-range offsets are dropped by the hardware, so the edge
+//    lanes need no branches.
+//  * Per cell: three v_max3_i32 and four adds (one v_add3_u32). The triple
+//    move's term is carried as D = (X6 of the previous slice), where
+//    X6 = M'(i,j-1,k-1) + C, so X7 = D + A + B needs no per-cell lookup;
+//    A and B are read once per row/column per step from byte tables with
+//    v_bfe_i32, keyed by a per-slice shift byte kept in LDS.
+//  * Predecessors outside the tensor hold a finite sentinel (kSent): row and
+//    column 0 use a table whose bytes are -128 and C = kSent, and the
+//    virtual row above the tensor holds 0 at (i=0, k=0), which seeds
+//    M'(0,0,0) = 0. No special edge code exists.
+//  * Batched triplets: a persistent grid; each wavefront pops triplets
+//    (longest first) and sweeps their panels in order, reusing its face
+//    buffers in place. One large triplet: panels spread over many
+//    wavefronts, faces handed over through HBM under per-panel progress
+//    counters (release/acquire at agent scope).
+#include <type_traits>
+
+#include "internal.h"
+
+namespace trioseq {
+namespace {
+
+constexpr int kBufFlags = 0x00020000;       // raw buffer, gfx9 family
+constexpr uint32_t kOob = 0xF0000000u;      // voffset outside every buffer
+
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* p, uint64_t bytes) {
+  const uint32_t n = bytes > 0x7FFFFFFFull ? 0x7FFFFFFFu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)n, kBufFlags);
+}
+
+__device__ __forceinline__ uint32_t residue_at(const uint32_t* __restrict__ words, uint64_t off,
+                                               uint32_t p) {
+  return (words[off + (p >> 4)] >> ((p & 15u) << 1)) & 3u;
+}
+
+__device__ __forceinline__ int sbyte(uint32_t tab, uint32_t sh) {
+  return __builtin_amdgcn_sbfe((int)tab, sh, 8);
+}
+
+__device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
+
+__device__ __forceinline__ uint32_t pick4(uint32_t code, uint32_t t0, uint32_t t1, uint32_t t2,
+                                          uint32_t t3) {
+  return code == 0 ? t0 : code == 1 ? t1 : code == 2 ? t2 : t3;
+}
+
+template <int RJ, int RK>
+struct Lds {
+  static constexpr int H = kGJ * RJ;
+  static constexpr int W = kGK * RK;
+  __attribute__((aligned(16))) int ringT[kRing][W];   // top face, entry e at slice s - e/RK
+  __attribute__((aligned(16))) int ringC[kRing][kGK]; // corner of top-edge lane x
+  __attribute__((aligned(16))) int ringL[kRing][H];   // left face, entry r at slice s - r/RJ
+  __attribute__((aligned(16))) int sR[64][RJ];        // right column of each lane
+  __attribute__((aligned(16))) int sB[64][RK];        // bottom row of each lane
+  int sX[64];                                         // bottom of each lane's left halo
+  int cap[RJ * RK];                                   // tile of the score cell at slice n0
+  int wsync;
+};
+
+struct PanelIO {
+  const int* top;     // bottom face of the panel above (padded rows), or a sentinel face
+  uint32_t top_stride;
+  const int* left;    // right face of the panel to the left, or a sentinel face
+  int* bot;           // this panel's bottom face (nullptr: not needed)
+  uint32_t bot_stride;
+  int* right;         // this panel's right face (nullptr: not needed)
+  const int* top_prog;
+  const int* left_prog;
+  int* my_prog;
+  int* err;           // set when a progress wait gave up
+};
+
+// Bounded wait for a neighbour panel's progress counter. Every wave leaves
+// the loop: after kSpinLimit polls it raises the error flag and proceeds
+// (the score is then marked invalid), so a lost producer cannot hang the GPU.
+constexpr int kSpinLimit = 1 << 21;
+
+__device__ __forceinline__ void wait_progress(const int* prog, int need, int* err) {
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    while (__hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      if (++spins > kSpinLimit) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ __forceinline__ void publish_progress(int* prog, int v) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (threadIdx.x == 0) __hip_atomic_store(prog, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-slice lookup shifts: shb[i + kFacePre] = 8 * code(S0[i-1]) for slices
+// 1..n0, 0 elsewhere; covers slices -kFacePre .. n0 + 47.
+__device__ __forceinline__ void stage_shifts(uint8_t* shb, const uint32_t* __restrict__ words,
+                                             const TripletDesc& td) {
+  const int n0 = (int)td.len[0];
+  const int total = n0 + 64;
+  for (int q = threadIdx.x; q < total; q += 64) {
+    const int i = q - kFacePre;
+    uint32_t v = 0;
+    if (i >= 1 && i <= n0) v = residue_at(words, td.off[0], (uint32_t)(i - 1)) << 3;
+    shb[q] = (uint8_t)v;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+}
+
+// One wavefront sweeps one panel over all slices.
+template <int RJ, int RK, bool WIDE>
+__device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring& sc,
+                            const uint32_t* __restrict__ words, const TripletDesc& td, int pj, int pk,
+                            const PanelIO& io, int32_t* score_out) {
+  constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
+  const int lane = threadIdx.x;
+  const int y = lane >> 3, x = lane & 7;
+  const int n0 = (int)td.len[0], n1 = (int)td.len[1], n2 = (int)td.len[2];
+  const int j0 = pj * H + y * RJ, k0 = pk * W + x * RK;
+  const uint32_t bt0 = sc.byte_tab[0], bt1 = sc.byte_tab[1], bt2 = sc.byte_tab[2],
+                 bt3 = sc.byte_tab[3], btz = sc.byte_tab[4];
+
+  // Row/column tables of this lane's tile.
+  uint32_t TB[RJ], TC[RK], cco[RK];
+#pragma unroll
+  for (int r = 0; r < RJ; ++r) {
+    const int j = j0 + r;
+    const uint32_t b = (j >= 1 && j <= n1) ? residue_at(words, td.off[1], (uint32_t)(j - 1)) : 0u;
+    TB[r] = j == 0 ? btz : pick4(b, bt0, bt1, bt2, bt3);
+  }
+#pragma unroll
+  for (int c = 0; c < RK; ++c) {
+    const int k = k0 + c;
+    cco[c] = (k >= 1 && k <= n2) ? residue_at(words, td.off[2], (uint32_t)(k - 1)) : 0u;
+    TC[c] = k == 0 ? btz : pick4(cco[c], bt0, bt1, bt2, bt3);
+  }
+  // C = s(b,c) - 2*gap (byte c of b's table, the matrix being symmetric),
+  // packed four per register; -128 on row 0 and column 0, where every
+  // predecessor that C is added to lies outside the tensor. The compiler
+  // folds the byte extraction into the add (SDWA).
+  constexpr int RKW = (RK + 3) / 4;
+  uint32_t Cp[RJ][RKW];
+#pragma unroll
+  for (int r = 0; r < RJ; ++r)
+#pragma unroll
+    for (int w = 0; w < RKW; ++w) {
+      uint32_t packed = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int cc = 4 * w + b;
+        if (cc >= RK) break;
+        const int v = (j0 + r == 0 || k0 + cc == 0) ? -128 : sbyte(TB[r], cco[cc] << 3);
+        packed |= (uint32_t)(v & 0xFF) << (8 * b);
+      }
+      Cp[r][w] = packed;
+    }
+
+  int P[RJ][RK], D[RJ][RK], Lp[RJ], Tp[RK];
+#pragma unroll
+  for (int r = 0; r < RJ; ++r) {
+    Lp[r] = kSent;
+#pragma unroll
+    for (int c = 0; c < RK; ++c) P[r][c] = D[r][c] = kSent;
+  }
+#pragma unroll
+  for (int c = 0; c < RK; ++c) Tp[c] = kSent;
+
+  const int nsteps = n0 + 1 + kSkew;
+  const int nchunks = (nsteps + kChunk - 1) / kChunk;
+  const int stepsp = nchunks * kChunk;
+
+  // The lane holding cell (n1, n2) of the last panel keeps slice n0.
+  const int rsel = n1 - j0, csel = n2 - k0;
+  const bool own = score_out && rsel >= 0 && rsel < RJ && csel >= 0 && csel < RK;
+
+  // Face resources. Rows are padded (kFacePre before slice 0), so every
+  // staging load and every edge store stays inside its buffer.
+  const uint32_t frows = face_rows((uint32_t)n0);
+  const Rsrc r_top = make_rsrc(io.top, (uint64_t)frows * io.top_stride * 4);
+  const Rsrc r_left = make_rsrc(io.left, (uint64_t)frows * RR * 4);
+  // An absent output gets an empty resource: its stores are all dropped.
+  const Rsrc r_bot = make_rsrc(io.bot ? io.bot : io.top,
+                               io.bot ? (uint64_t)frows * io.bot_stride * 4 : 0);
+  const Rsrc r_right = make_rsrc(io.right ? io.right : io.left,
+                                 io.right ? (uint64_t)frows * RR * 4 : 0);
+  const uint32_t ts = io.top_stride, bs = io.bot_stride;
+
+  // Staging. Value q of a chunk is, for this lane, entry v = lane + 64 q of
+  // one of three LDS rings (top face, corners, left face). Within a ring a
+  // q step advances by whole rows (ring widths divide 64), so each ring needs
+  // one base voffset per lane plus a scalar increment per q, and the LDS
+  // destination is simply ring base + v. Faces always exist: at the tensor
+  // edge they are sentinel buffers, and padding rows hold the fill-phase
+  // values of the producing panel, which stay within 2^24 of kSent.
+  constexpr int QT = kChunk * W / 64, QC = kChunk * kGK / 64, QL = kChunk * H / 64;
+  constexpr int NPF = QT + QC + QL;
+  constexpr int RT = 64 / W, RL = 64 / H;  // ring rows per q
+  static_assert(64 % W == 0 && 64 % H == 0 && QC == 1, "ring widths must divide 64");
+  const int eT = lane % W;
+  const uint32_t offT = (uint32_t)(((kFacePre + lane / W - eT / RK) * (int)ts + eT) * 4);
+  const int eC = lane % kGK;
+  const bool corner_from_left = eC == 0;
+  const uint32_t offC = corner_from_left
+                            ? (uint32_t)((kFacePre + lane / kGK) * RR * 4)
+                            : (uint32_t)(((kFacePre + lane / kGK - eC) * (int)ts + eC * RK - 1) * 4);
+  const int eL = lane % H;
+  const uint32_t offL = (uint32_t)(((kFacePre + lane / H - eL / RJ) * RR + 4 + eL) * 4);
+
+  int pf[NPF];
+  auto stage_load = [&](int c) {
+    const uint32_t base = (uint32_t)(c * kChunk);
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      int v;
+      if (q < QT) {
+        v = __builtin_amdgcn_raw_buffer_load_b32(r_top, offT, (base + q * RT) * ts * 4u, 0);
+      } else if (q < QT + QC) {
+        const int a = __builtin_amdgcn_raw_buffer_load_b32(r_top, corner_from_left ? kOob : offC,
+                                                           base * ts * 4u, 0);
+        const int b = __builtin_amdgcn_raw_buffer_load_b32(r_left, corner_from_left ? offC : kOob,
+                                                           base * RR * 4u, 0);
+        v = a | b;
+      } else {
+        v = __builtin_amdgcn_raw_buffer_load_b32(r_left, offL,
+                                                 (base + (q - QT - QC) * RL) * RR * 4u, 0);
+      }
+      pf[q] = v;
+    }
+  };
+  auto stage_finish = [&](int c) {
+    const int rr = (c & 1) * kChunk;
+    int* rt = &L.ringT[rr][0];
+    int* rc = &L.ringC[rr][0];
+    int* rl = &L.ringL[rr][0];
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      if (q < QT)
+        rt[lane + 64 * q] = pf[q];
+      else if (q < QT + QC)
+        rc[lane] = pf[q];
+      else
+        rl[lane + 64 * (q - QT - QC)] = pf[q];
+    }
+  };
+
+  if (WIDE) {
+    const int need = min(2 * kChunk, stepsp);
+    if (io.top_prog) wait_progress(io.top_prog, need, io.err);
+    if (io.left_prog) wait_progress(io.left_prog, need, io.err);
+  }
+  stage_load(0);
+  // Before step 0 the neighbour slots hold slice "-1" for every lane: the
+  // sentinel (they are read at step 0, before any lane has written them).
+#pragma unroll
+  for (int r = 0; r < RJ; ++r) L.sR[lane][r] = kSent;
+#pragma unroll
+  for (int c = 0; c < RK; ++c) L.sB[lane][c] = kSent;
+  L.sX[lane] = kSent;
+
+  // Per-lane LDS sources of the three halos: ring rows for edge lanes,
+  // neighbour slots (written one step earlier) otherwise.
+  const bool y0 = y == 0, x0 = x == 0;
+  const int* t_base = y0 ? &L.ringT[0][x * RK] : &L.sB[y0 ? 0 : lane - 8][0];
+  const int t_str = y0 ? W : 0;
+  const int* c_base = y0 ? &L.ringC[0][x] : &L.sX[y0 ? 0 : lane - 8];
+  const int c_str = y0 ? kGK : 0;
+  const int* l_base = x0 ? &L.ringL[0][y * RJ] : &L.sR[x0 ? 0 : lane - 1][0];
+  const int l_str = x0 ? H : 0;
+
+  // Edge stores: bottom row (y = 7), right column (x = 7), and the corner
+  // for the next panel (lane (0,7)). The row of slice i is i + kFacePre.
+  const uint32_t vo_bot =
+      (y == kGJ - 1) ? (uint32_t)(((kFacePre - y - x) * (int)bs + x * RK) * 4) : kOob;
+  const uint32_t vo_right =
+      (x == kGK - 1) ? (uint32_t)(((kFacePre - y - x) * RR + 4 + y * RJ) * 4) : kOob;
+  const uint32_t vo_corner = (x == kGK - 1 && y == 0) ? (uint32_t)((kFacePre - x) * RR * 4) : kOob;
+  const int sh_base = kFacePre - y - x;
+
+  auto run_chunk = [&](int c, bool cap) {
+    const int rr = (c & 1) * kChunk;
+    const int* tb = t_base + rr * t_str;
+    const int* cb = c_base + rr * c_str;
+    const int* lb = l_base + rr * l_str;
+    const uint8_t* sp = shb + sh_base + c * kChunk;
+#pragma unroll
+    for (int s = 0; s < kChunk; ++s) {
+      const int t = c * kChunk + s;
+      const uint32_t sh = sp[s];
+      int A[RJ], B[RK];
+#pragma unroll
+      for (int r = 0; r < RJ; ++r) A[r] = sbyte(TB[r], sh);
+#pragma unroll
+      for (int cc = 0; cc < RK; ++cc) B[cc] = sbyte(TC[cc], sh);
+      int T[RK], Lh[RJ];
+      const int* tp = tb + s * t_str;
+      const int* lp = lb + s * l_str;
+#pragma unroll
+      for (int cc = 0; cc < RK; ++cc) T[cc] = tp[cc];
+#pragma unroll
+      for (int r = 0; r < RJ; ++r) Lh[r] = lp[r];
+      const int corner = cb[s * c_str];
+
+      int N[RJ][RK];
+#pragma unroll
+      for (int r = 0; r < RJ; ++r) {
+#pragma unroll
+        for (int cc = 0; cc < RK; ++cc) {
+          const int up_cur = r ? N[r - 1][cc] : T[cc];
+          const int up_prev = r ? P[r - 1][cc] : Tp[cc];
+          const int left_cur = cc ? N[r][cc - 1] : Lh[r];
+          const int left_prev = cc ? P[r][cc - 1] : Lp[r];
+          const int diag_cur = r ? (cc ? N[r - 1][cc - 1] : Lh[r - 1]) : (cc ? T[cc - 1] : corner);
+          const int x4 = up_prev + A[r];
+          const int x5 = left_prev + B[cc];
+          const int x6 = diag_cur + (int)(int8_t)(uint8_t)(Cp[r][cc >> 2] >> (8 * (cc & 3)));
+          const int x7 = D[r][cc] + A[r] + B[cc];
+          N[r][cc] = max3i(max3i(P[r][cc], up_cur, left_cur), max3i(x4, x5, x6), x7);
+          D[r][cc] = x6;
+        }
+      }
+
+#pragma unroll
+      for (int r = 0; r < RJ; ++r) L.sR[lane][r] = N[r][RK - 1];
+#pragma unroll
+      for (int cc = 0; cc < RK; ++cc) L.sB[lane][cc] = N[RJ - 1][cc];
+      L.sX[lane] = Lh[RJ - 1];
+
+      // Edge stores (the hardware drops lanes whose offset is kOob).
+#pragma unroll
+      for (int cc = 0; cc < RK; cc += 4)
+        __builtin_amdgcn_raw_buffer_store_b128(
+            (__attribute__((ext_vector_type(4))) int){N[RJ - 1][cc], N[RJ - 1][cc + 1],
+                                                     N[RJ - 1][cc + 2], N[RJ - 1][cc + 3]},
+            r_bot, vo_bot + cc * 4, (uint32_t)t * bs * 4u, 0);
+#pragma unroll
+      for (int r = 0; r < RJ; r += 4)
+        __builtin_amdgcn_raw_buffer_store_b128(
+            (__attribute__((ext_vector_type(4))) int){N[r][RK - 1], N[r + 1][RK - 1],
+                                                     N[r + 2][RK - 1], N[r + 3][RK - 1]},
+            r_right, vo_right + r * 4, (uint32_t)t * RR * 4u, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(T[RK - 1], r_right, vo_corner, (uint32_t)t * RR * 4u, 0);
+
+      if (cap) {
+        if (own && t - y - x == n0) {
+#pragma unroll
+          for (int r = 0; r < RJ; ++r)
+#pragma unroll
+            for (int cc = 0; cc < RK; ++cc) L.cap[r * RK + cc] = N[r][cc];
+        }
+      }
+
+#pragma unroll
+      for (int r = 0; r < RJ; ++r) {
+        Lp[r] = Lh[r];
+#pragma unroll
+        for (int cc = 0; cc < RK; ++cc) P[r][cc] = N[r][cc];
+      }
+#pragma unroll
+      for (int cc = 0; cc < RK; ++cc) Tp[cc] = T[cc];
+    }
+  };
+
+  for (int c = 0; c < nchunks; ++c) {
+    stage_finish(c);
+    if (c + 1 < nchunks) {
+      if (WIDE) {
+        const int need = min((c + 3) * kChunk, stepsp);
+        if (io.top_prog) wait_progress(io.top_prog, need, io.err);
+        if (io.left_prog) wait_progress(io.left_prog, need, io.err);
+      }
+      stage_load(c + 1);
+    }
+    const bool cap_chunk =
+        score_out != nullptr && n0 >= c * kChunk - kSkew && n0 <= c * kChunk + kChunk - 1;
+    run_chunk(c, cap_chunk);
+    if (WIDE && io.my_prog) publish_progress(io.my_prog, (c + 1) * kChunk);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  if (own) *score_out = L.cap[rsel * RK + csel] + sc.gap2 * (n0 + n1 + n2);
+}
+
+template <int RJ, int RK>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RJ * RK <= 16 ? 4 : 2))) k_batch(BatchArgs a) {
+  constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
+  __shared__ Lds<RJ, RK> L;
+  extern __shared__ uint8_t shb[];
+  int* face = a.face + (uint64_t)blockIdx.x * a.face_stride;
+  for (;;) {
+    if (threadIdx.x == 0) L.wsync = atomicAdd(a.counter, 1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    const int idx = __builtin_amdgcn_readfirstlane(L.wsync);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    if (idx >= (int)a.n) break;
+    const TripletDesc td = a.desc[idx];
+    stage_shifts(shb, a.words, td);
+    const int n0 = (int)td.len[0], n1 = (int)td.len[1], n2 = (int)td.len[2];
+    const int PJ = n1 / H + 1, PK = n2 / W + 1;
+    const uint32_t fr_rows = face_rows((uint32_t)n0);
+    int* fb = face;
+    int* fr = face + (uint64_t)fr_rows * (uint64_t)(PK * W);
+    for (int pj = 0; pj < PJ; ++pj) {
+      for (int pk = 0; pk < PK; ++pk) {
+        PanelIO io;
+        io.top = pj ? fb + pk * W : (pk ? a.bnd_top : a.bnd_top_seed);
+        io.top_stride = pj ? (uint32_t)(PK * W) : (uint32_t)W;
+        io.left = pk ? fr : a.bnd_left;
+        io.bot = pj + 1 < PJ ? fb + pk * W : nullptr;
+        io.bot_stride = (uint32_t)(PK * W);
+        io.right = pk + 1 < PK ? fr : nullptr;
+        io.top_prog = io.left_prog = nullptr;
+        io.my_prog = nullptr;
+        io.err = nullptr;
+        int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
+        sweep_panel<RJ, RK, false>(L, shb, a.sc, a.words, td, pj, pk, io, so);
+      }
+    }
+    (void)RR;
+  }
+}
+
+template <int RJ, int RK>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RJ * RK <= 16 ? 4 : 2))) k_wide(WideArgs a) {
+  constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
+  __shared__ Lds<RJ, RK> L;
+  extern __shared__ uint8_t shb[];
+  const TripletDesc td = a.desc;
+  stage_shifts(shb, a.words, td);
+  const int n0 = (int)td.len[0], n1 = (int)td.len[1], n2 = (int)td.len[2];
+  const int PJ = n1 / H + 1, PK = n2 / W + 1;
+  const uint64_t rows = face_rows((uint32_t)n0);
+  const uint64_t fb_ints = rows * W;
+  const uint64_t per_panel = fb_ints + rows * RR;
+  for (uint32_t q = 0; q < a.panels_per_wave; ++q) {
+    const uint32_t p = a.order[(uint64_t)blockIdx.x * a.panels_per_wave + q];
+    if (p >= a.n_panels) break;
+    const int pj = (int)(p / a.pk_count), pk = (int)(p % a.pk_count);
+    int* base = a.face + (uint64_t)p * per_panel;
+    PanelIO io;
+    io.top = pj ? a.face + (uint64_t)(p - a.pk_count) * per_panel : (pk ? a.bnd_top : a.bnd_top_seed);
+    io.top_stride = W;
+    io.left = pk ? a.face + (uint64_t)(p - 1) * per_panel + fb_ints : a.bnd_left;
+    io.bot = pj + 1 < PJ ? base : nullptr;
+    io.bot_stride = W;
+    io.right = pk + 1 < PK ? base + fb_ints : nullptr;
+    io.top_prog = pj ? a.progress + (p - a.pk_count) : nullptr;
+    io.left_prog = pk ? a.progress + (p - 1) : nullptr;
+    io.my_prog = a.progress + p;
+    io.err = a.progress + a.n_panels;
+    int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
+    sweep_panel<RJ, RK, true>(L, shb, a.sc, a.words, td, pj, pk, io, so);
+    if (so && threadIdx.x == 0 &&
+        __hip_atomic_load(io.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+      *so = INT32_MIN;
+  }
+}
+
+// Sentinel faces for panels on the tensor edge: every entry kSent, except
+// the seeded top face, whose entry for k = 0 at slice 0 is 0 (it makes
+// M'(0,0,0) = 0 through the move from the virtual row above).
+__global__ void k_init_boundary(int* top_seed, int* top, int* left, int top_ints, int left_ints,
+                                int seed_index) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < top_ints; i += gridDim.x * blockDim.x) {
+    top_seed[i] = i == seed_index ? 0 : kSent;
+    top[i] = kSent;
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < left_ints; i += gridDim.x * blockDim.x)
+    left[i] = kSent;
+}
+
+__global__ void k_reset(int* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+#define TRIOSEQ_SHAPES(X) X(4, 4) X(8, 4) X(4, 8)
+
+}  // namespace
+
+bool shape_supported(const KernelShape& ks) {
+#define X(a, b) if (ks.rj == a && ks.rk == b) return true;
+  TRIOSEQ_SHAPES(X)
+#undef X
+  return false;
+}
+
+hipError_t launch_init_boundary(const KernelShape& ks, const Boundary& b, hipStream_t s) {
+  const int W = panel_cols(ks), RR = right_face_row(ks);
+  const int top_ints = (int)b.rows * W, left_ints = (int)b.rows * RR;
+  hipLaunchKernelGGL(k_init_boundary, dim3(256), dim3(256), 0, s, b.top_seed, b.top, b.left,
+                     top_ints, left_ints, kFacePre * W);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset(int* p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int grid = (n + 255) / 256;
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(k_reset, dim3(grid), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const KernelShape& ks, const BatchArgs& a, int grid, hipStream_t s) {
+  const size_t lds = shift_lds_bytes(a.lds_n0);
+#define X(r, c)                                                                \
+  if (ks.rj == r && ks.rk == c) {                                              \
+    hipLaunchKernelGGL((k_batch<r, c>), dim3(grid), dim3(64), lds, s, a);      \
+    return hipGetLastError();                                                  \
+  }
+  TRIOSEQ_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_wide(const KernelShape& ks, const WideArgs& a, int grid, hipStream_t s) {
+  const size_t lds = shift_lds_bytes(a.desc.len[0]);
+#define X(r, c)                                                                \
+  if (ks.rj == r && ks.rk == c) {                                              \
+    hipLaunchKernelGGL((k_wide<r, c>), dim3(grid), dim3(64), lds, s, a);       \
+    return hipGetLastError();                                                  \
+  }
+  TRIOSEQ_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t batch_occupancy(const KernelShape& ks, uint32_t lds_n0, int* waves_per_cu) {
+#define X(r, c)                                                                               \
+  if (ks.rj == r && ks.rk == c)                                                               \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_batch<r, c>, 64,       \
+                                                        shift_lds_bytes(lds_n0));
+  TRIOSEQ_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t wide_occupancy(const KernelShape& ks, uint32_t lds_n0, int* waves_per_cu) {
+#define X(r, c)                                                                               \
+  if (ks.rj == r && ks.rk == c)                                                               \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_wide<r, c>, 64,        \
+                                                        shift_lds_bytes(lds_n0));
+  TRIOSEQ_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+}  // namespace trioseq

@@ -1,0 +1,114 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+and rejects bad input before any device call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2605_28400_amd as ts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "trioseq.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(trioseq_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ts.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(ts.EXPORTS) == names
+
+
+def test_version_string():
+    assert "gfx950" in ts.version()
+
+
+def test_pack_layout_and_bits():
+    w = ts.pack("ACGTACGTACGTACGTT")
+    assert w.dtype == np.uint32 and w.size == 2
+    # A=0 C=1 G=2 T=3, residue p at bits 2*(p%16).
+    want0 = sum(c << (2 * p) for p, c in enumerate([0, 1, 2, 3] * 4))
+    assert int(w[0]) == want0 and int(w[1]) == 3
+    assert ts.pack("acgt").tolist() == ts.pack("ACGT").tolist()
+    assert ts.pack("").size == 0
+
+
+def test_packed_layout_offsets():
+    lens, off, words = ts.pack_batch([("A" * 17, "", "C" * 16), ("G", "T" * 33, "A")])
+    assert lens.tolist() == [17, 0, 16, 1, 33, 1]
+    assert off.tolist() == [0, 2, 2, 3, 4, 7]
+    assert words.size == 8
+
+
+def _status(fn):
+    with pytest.raises(ts.TrioseqError) as e:
+        fn()
+    return e.value.status
+
+
+def test_bad_residue_rejected():
+    assert _status(lambda: ts.pack("ACGN")) == -2
+    assert _status(lambda: ts.score(("ACGT", "ACXT", "A"))) == -2
+    assert "triplet 1" in str(pytest.raises(ts.TrioseqError, ts.score_batch,
+                                            [("A", "C", "G"), ("A", "-", "G")]).value)
+
+
+def test_asymmetric_matrix_rejected():
+    sub = np.full((4, 4), -1)
+    np.fill_diagonal(sub, 1)
+    sub[0, 1] = 2
+    assert _status(lambda: ts.score(("A", "C", "G"), ts.scoring(sub=sub, gap=-2))) == -1
+
+
+def test_byte_range_of_terms_rejected():
+    assert _status(lambda: ts.score(("A", "C", "G"), ts.scoring(1, -1, gap=-70))) == -1
+    assert _status(lambda: ts.score(("A", "C", "G"), ts.scoring(130, -1, gap=0))) == -1
+
+
+def test_overflow_bound_rejected():
+    # (a+b+c) * max(sub - 2*gap) must stay below 2^27.
+    long, short = "A" * 1_200_000, "A" * 10
+    assert _status(lambda: ts.score((long, long, short), ts.scoring(100, -1, gap=-10))) == -4
+
+
+def test_too_large_rejected():
+    L = ts.lib()
+    lens = np.array([20000, 20000, 20000], dtype=np.uint32)
+    h = ctypes.c_void_p()
+    st = L.trioseq_plan_create(lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), None, 1,
+                               ctypes.byref(ts.scoring()), None, ctypes.byref(h))
+    assert st == -3
+
+
+def test_null_pointers_rejected():
+    L = ts.lib()
+    assert L.trioseq_score(None, None, None) == -1
+    out = ctypes.c_int32(123)
+    tr = ts.Triplet()
+    tr.len[0] = 3
+    tr.seq[0] = None
+    assert L.trioseq_score(ctypes.byref(tr), ctypes.byref(ts.scoring()), ctypes.byref(out)) == -1
+    assert out.value == 123  # untouched on error
+    assert L.trioseq_plan_create(None, None, 1, ctypes.byref(ts.scoring()), None, None) == -1
+    assert L.trioseq_plan_run(None, None, None, None) == -1
+    assert b"NULL" in L.trioseq_last_error() or L.trioseq_last_error()
+
+
+def test_bad_plan_options_rejected():
+    L = ts.lib()
+    lens = np.array([3, 3, 3], dtype=np.uint32)
+    h = ctypes.c_void_p()
+    for opts in [ts.PlanOptions(5, 0, 0, 0, 0), ts.PlanOptions(-1, 3, 3, 0, 0),
+                 ts.PlanOptions(-1, 0, 0, -4, 0)]:
+        assert L.trioseq_plan_create(lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), None, 1,
+                                     ctypes.byref(ts.scoring()), ctypes.byref(opts),
+                                     ctypes.byref(h)) == -1
