@@ -1,0 +1,164 @@
+"""Throughput benchmark of exact global 3-way alignment scoring on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one scoring pass of the whole hot path over the workload's batch,
+with the packed residues already resident in HBM. The default workload is the
+single mutated-ancestor triplet of lengths 1024/1000/1048 (1.07e9 cells).
+Prints one JSON line: GCUPS (10^9 cell updates/s, cells = a*b*c per
+triplet), the INT32 VALU roofline of the dominant kernel, and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 int32 lane-ops/s.
+PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic VALU work per cell: 4 adds + 3 three-input maxima (the shifted
+# recurrence of Eq. 1 with hoisted substitution terms).
+OPS_PER_CELL = 7
+
+WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="single_1k", choices=WORKLOADS)
+    ap.add_argument("--tile", default="0x0", help="lane tile RJxRK (0x0 = library default)")
+    ap.add_argument("--engine", type=int, default=-1)
+    ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(workload, budget_s: float = 20.0):
+    """The oracle, as is, on a bounded sample of the workload (host cores)."""
+    import oracle
+    from paper_2605_28400_amd import synth
+    trips = workload.triplets
+    cores = 1 if len(trips) == 1 else (os.cpu_count() or 1)
+    if len(trips) == 1:
+        t = trips[0]
+        cells = synth.cells(t)
+        if cells > 3e9:
+            # A prefix of the sweep sequence: same shape class, bounded time.
+            n0 = max(1, int(2e9 / (t[1].size * t[2].size)))
+            t = (t[0][:n0], t[1], t[2])
+            sample = f"first {n0} residues of the sweep sequence x full other two (1 thread)"
+        else:
+            sample = "the whole triplet (1 thread)"
+        cells = synth.cells(t)
+        t0 = time.perf_counter()
+        score = oracle.score(t)
+        dt = time.perf_counter() - t0
+        return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": cores, "kind": "oracle",
+                "sample": sample, "seconds": round(dt, 3)}, score
+    # Batched: as many triplets (in workload order) as fit the time budget
+    # at the oracle's measured rate, on all host cores.
+    probe = trips[:cores]
+    t0 = time.perf_counter()
+    oracle.score_batch(probe, threads=cores)
+    rate = sum(synth.cells(t) for t in probe) / max(time.perf_counter() - t0, 1e-6)
+    take, acc = 0, 0.0
+    for t in trips:
+        acc += synth.cells(t)
+        take += 1
+        if acc > rate * budget_s:
+            break
+    sample = trips[:take]
+    cells = sum(synth.cells(t) for t in sample)
+    t0 = time.perf_counter()
+    oracle.score_batch(sample, threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": cores, "kind": "oracle",
+            "sample": f"first {take} of {len(trips)} triplets on {cores} threads",
+            "seconds": round(dt, 3)}, None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: every workload here is measured on a single "
+              "MI355X (see DESIGN.md for how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2605_28400_amd as ts
+    from paper_2605_28400_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    workload = synth.WORKLOADS[args.workload]()
+    trips = workload.triplets
+    lens, off, words = ts.pack_batch(trips)
+    rj, rk = (int(v) for v in args.tile.split("x"))
+    plan = ts.Plan(lens, off, engine=args.engine, tile=(rj, rk), use_graph=bool(args.graph))
+    info = plan.info()
+    d_words = torch.from_numpy(words.view(np.int32)).cuda()
+    d_scores = torch.zeros(len(trips), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.run(d_words, d_scores, stream)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        plan.run(d_words, d_scores, stream)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_events = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+
+    cells = float(workload.total_cells)
+    ms_per_step = wall * 1e3 / args.steps
+    gcups = cells / (ms_per_step * 1e-3) / 1e9
+    achieved = cells * OPS_PER_CELL / (ms_events * 1e-3) / 1e12
+    scores = d_scores.cpu().numpy()
+
+    rec = {
+        "metric": "GCUPS", "value": round(gcups, 3), "unit": "GCUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": workload.name, "triplets": len(trips), "cells": int(cells),
+                   "seed": workload.seed, "scoring": "match +1, mismatch -1, gap -2",
+                   "engine": ["batch", "wide"][info["engine"]],
+                   "tile": f"{info['tile_rows']}x{info['tile_cols']}", "grid": info["grid"],
+                   "hip_graph": bool(args.graph), "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOP/s",
+                     "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
+                     "kernel_ms": round(ms_events, 4), "ops_per_cell": OPS_PER_CELL,
+                     "kernel": "k_wide (one triplet over many wavefronts)" if info["engine"] == 1
+                     else "k_batch (persistent, one triplet per wavefront)"},
+    }
+    if not args.no_cpu_baseline:
+        cb, oracle_score = cpu_baseline(workload)
+        rec["cpu_baseline"] = cb
+        if oracle_score is not None and len(trips) == 1 and cb["sample"].startswith("the whole"):
+            rec["parity_vs_oracle"] = bool(int(scores[0]) == oracle_score)
+    print(json.dumps(rec), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

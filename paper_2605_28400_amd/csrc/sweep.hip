@@ -102,6 +102,15 @@ struct PanelIO {
   int* err;           // set when a progress wait gave up
 };
 
+// Cross-wavefront hand-over in the wide engine. Face values are written and
+// read with device-coherent buffer accesses (the SC1 cache-policy bit: the
+// same per-instruction coherence the compiler uses for relaxed agent-scope
+// atomics), so no cache-wide write-back or invalidate is ever needed. The
+// producer waits for its face stores to complete (s_waitcnt vmcnt(0)) before
+// it publishes the count of finished steps; the consumer polls that count.
+constexpr int kCohNone = 0;
+constexpr int kCohDevice = 16;  // SC1
+
 // Bounded wait for a neighbour panel's progress counter. Every wave leaves
 // the loop: after kSpinLimit polls it raises the error flag and proceeds
 // (the score is then marked invalid), so a lost producer cannot hang the GPU.
@@ -118,11 +127,14 @@ __device__ __forceinline__ void wait_progress(const int* prog, int need, int* er
       __builtin_amdgcn_s_sleep(2);
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  // Face loads must not be hoisted above the poll.
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 __device__ __forceinline__ void publish_progress(int* prog, int v) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);  // every face store of this wave has completed
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
   if (threadIdx.x == 0) __hip_atomic_store(prog, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -147,6 +159,7 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
                             const uint32_t* __restrict__ words, const TripletDesc& td, int pj, int pk,
                             const PanelIO& io, int32_t* score_out) {
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
+  constexpr int COH = WIDE ? kCohDevice : kCohNone;
   const int lane = threadIdx.x;
   const int y = lane >> 3, x = lane & 7;
   const int n0 = (int)td.len[0], n1 = (int)td.len[1], n2 = (int)td.len[2];
@@ -247,16 +260,16 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
     for (int q = 0; q < NPF; ++q) {
       int v;
       if (q < QT) {
-        v = __builtin_amdgcn_raw_buffer_load_b32(r_top, offT, (base + q * RT) * ts * 4u, 0);
+        v = __builtin_amdgcn_raw_buffer_load_b32(r_top, offT, (base + q * RT) * ts * 4u, COH);
       } else if (q < QT + QC) {
         const int a = __builtin_amdgcn_raw_buffer_load_b32(r_top, corner_from_left ? kOob : offC,
-                                                           base * ts * 4u, 0);
+                                                           base * ts * 4u, COH);
         const int b = __builtin_amdgcn_raw_buffer_load_b32(r_left, corner_from_left ? offC : kOob,
-                                                           base * RR * 4u, 0);
+                                                           base * RR * 4u, COH);
         v = a | b;
       } else {
         v = __builtin_amdgcn_raw_buffer_load_b32(r_left, offL,
-                                                 (base + (q - QT - QC) * RL) * RR * 4u, 0);
+                                                 (base + (q - QT - QC) * RL) * RR * 4u, COH);
       }
       pf[q] = v;
     }
@@ -365,14 +378,14 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
         __builtin_amdgcn_raw_buffer_store_b128(
             (__attribute__((ext_vector_type(4))) int){N[RJ - 1][cc], N[RJ - 1][cc + 1],
                                                      N[RJ - 1][cc + 2], N[RJ - 1][cc + 3]},
-            r_bot, vo_bot + cc * 4, (uint32_t)t * bs * 4u, 0);
+            r_bot, vo_bot + cc * 4, (uint32_t)t * bs * 4u, COH);
 #pragma unroll
       for (int r = 0; r < RJ; r += 4)
         __builtin_amdgcn_raw_buffer_store_b128(
             (__attribute__((ext_vector_type(4))) int){N[r][RK - 1], N[r + 1][RK - 1],
                                                      N[r + 2][RK - 1], N[r + 3][RK - 1]},
-            r_right, vo_right + r * 4, (uint32_t)t * RR * 4u, 0);
-      __builtin_amdgcn_raw_buffer_store_b32(T[RK - 1], r_right, vo_corner, (uint32_t)t * RR * 4u, 0);
+            r_right, vo_right + r * 4, (uint32_t)t * RR * 4u, COH);
+      __builtin_amdgcn_raw_buffer_store_b32(T[RK - 1], r_right, vo_corner, (uint32_t)t * RR * 4u, COH);
 
       if (cap) {
         if (own && t - y - x == n0) {
