@@ -28,7 +28,7 @@ PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # recurrence of Eq. 1 with hoisted substitution terms).
 OPS_PER_CELL = 7
 
-WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k")
+WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served")
 
 
 def parse():
@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--engine", type=int, default=-1)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=4000, help="served: stream length")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="served: offered load as a fraction of measured batched throughput")
     return ap.parse_args()
 
 
@@ -88,8 +91,80 @@ def cpu_baseline(workload, budget_s: float = 20.0):
             "seconds": round(dt, 3)}, None
 
 
+def served(args):
+    """Poisson stream through the continuous-batching server.
+
+    The arrival rate is load x (batched throughput of the same requests
+    scored in one plan) / mean cells per request. Reports sustained GCUPS
+    (cells of completed requests / first submit to last completion) and the
+    submit-to-result latency percentiles.
+    """
+    import torch
+    import paper_2605_28400_amd as ts
+    from paper_2605_28400_amd import synth
+    workload, gaps = synth.served_stream(count=args.requests)
+    trips = workload.triplets
+    cells = float(workload.total_cells)
+    # Batched throughput of the same requests, as one plan.
+    lens, off, words = ts.pack_batch(trips)
+    plan = ts.Plan(lens, off, use_graph=False)
+    d_words = torch.from_numpy(words.view(np.int32)).cuda()
+    d_scores = torch.zeros(len(trips), dtype=torch.int32, device="cuda")
+    plan.run(d_words, d_scores)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(d_words, d_scores)
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t0
+    batch_scores = d_scores.cpu().numpy()
+    plan.close()
+    batch_gcups = cells / batch_s / 1e9
+    rate = args.load * (cells / batch_s) / (cells / len(trips))  # requests per second
+    srv = ts.Server(max_len=2048, max_device_bytes=96 << 30)
+    arrivals = np.cumsum(gaps / rate)
+    ids = []
+    start = time.perf_counter()
+    for k, t in enumerate(trips):
+        delay = arrivals[k] - (time.perf_counter() - start)
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(t))
+        if k % 200 == 0:
+            print(f"submitted {k}/{len(trips)}", file=sys.stderr, flush=True)
+    res = {}
+    last = 0
+    for rid in ids:
+        r = srv.wait(rid, timeout_s=600)
+        res[rid] = r
+        last = max(last, r["t_done_ns"])
+    st = srv.stats()
+    first = min(r["t_submit_ns"] for r in res.values())
+    srv.close()
+    served_s = (last - first) * 1e-9
+    ok = all(r["status"] == 0 for r in res.values())
+    same = all(res[rid]["score"] == int(batch_scores[k]) for k, rid in enumerate(ids))
+    rec = {
+        "metric": "GCUPS", "value": round(cells / served_s / 1e9, 3), "unit": "GCUPS", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(served_s * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": workload.name, "requests": len(trips), "cells": int(cells),
+                   "seed": workload.seed, "arrivals": "Poisson", "rate_req_per_s": round(rate, 1),
+                   "offered_load": args.load, "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(st["p50_ns"] / 1e6, 3), "p99": round(st["p99_ns"] / 1e6, 3)},
+        "rounds": st["rounds"], "batched_gcups_same_requests": round(batch_gcups, 3),
+        "all_ok": ok, "served_equals_batched": same,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "served":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only.", file=sys.stderr)
+            sys.exit(2)
+        served(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: every workload here is measured on a single "
               "MI355X (see DESIGN.md for how the path would shard).", file=sys.stderr)

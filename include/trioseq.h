@@ -90,18 +90,23 @@ trioseq_status trioseq_score_batch(const trioseq_triplet* t, size_t n, const tri
 typedef struct trioseq_plan trioseq_plan;
 
 typedef struct trioseq_plan_options {
-  int32_t engine;    /* -1 auto; 0 = batch (one wavefront per triplet, persistent
-                        queue); 1 = wide (one triplet over many wavefronts) */
-  int32_t tile_rows; /* lane tile rows; 0 = automatic (tuned table or default) */
-  int32_t tile_cols; /* lane tile columns; 0 = automatic */
-  int32_t grid;      /* wavefronts to launch; 0 = fill the device */
-  int32_t use_graph; /* 1 = capture the launch sequence in a hipGraph and replay it */
+  int32_t engine;         /* -1 auto (a lone triplet and very large ones are split
+                             into panel jobs, the rest swept whole); 0 = every
+                             triplet whole (one wavefront each); 1 = every triplet
+                             split into panel jobs over many wavefronts */
+  int32_t tile_rows;      /* lane tile rows; 0 = default (4) */
+  int32_t tile_cols;      /* lane tile columns; 0 = default (4) */
+  int32_t grid;           /* wavefronts to launch; 0 = fill the device */
+  int32_t use_graph;      /* 1 = capture the launch sequence in a hipGraph and replay it */
+  int32_t waves_per_simd; /* register budget of the kernel: 4 or 2; 0 = default */
 } trioseq_plan_options;
 
 typedef struct trioseq_plan_info {
-  int32_t engine, tile_rows, tile_cols, grid, waves_per_cu, panels;
+  int32_t engine;         /* 0 all whole, 1 all split, 2 mixed */
+  int32_t tile_rows, tile_cols, grid, waves_per_cu;
+  int32_t panels;         /* panel jobs of split triplets */
   uint64_t workspace_bytes;
-  double cells; /* sum of a*b*c over the batch */
+  double cells;           /* sum of a*b*c over the batch */
 } trioseq_plan_info;
 
 /* Plans scores for n triplets whose lengths are lens[3t+s] (host array) and

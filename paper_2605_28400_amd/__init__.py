@@ -38,7 +38,7 @@ class Triplet(ctypes.Structure):
 class PlanOptions(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("tile_cols", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -237,14 +237,14 @@ class Plan:
     """Device-resident batch plan: ``run`` enqueues one scoring pass on a stream."""
 
     def __init__(self, lens, word_off=None, sc: Scoring | None = None, engine: int = -1,
-                 tile=(0, 0), grid: int = 0, use_graph: bool = False):
+                 tile=(0, 0), grid: int = 0, use_graph: bool = False, waves_per_simd: int = 0):
         self.lens = np.ascontiguousarray(lens, dtype=np.uint32)
         self.n = self.lens.size // 3
         off_p = None
         if word_off is not None:
             self._off = np.ascontiguousarray(word_off, dtype=np.uint64)
             off_p = self._off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
-        opts = PlanOptions(engine, tile[0], tile[1], grid, 1 if use_graph else 0)
+        opts = PlanOptions(engine, tile[0], tile[1], grid, 1 if use_graph else 0, waves_per_simd)
         self._h = ctypes.c_void_p()
         check(lib().trioseq_plan_create(self.lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                         off_p, self.n, ctypes.byref(sc or _default_scoring()),
@@ -279,3 +279,54 @@ class Plan:
 
 def version() -> str:
     return lib().trioseq_version().decode()
+
+
+class Server:
+    """Continuous-batching scoring server (one GPU, background device thread)."""
+
+    def __init__(self, max_len: int = 2048, sc: Scoring | None = None, device: int = 0,
+                 max_queue: int = 0, max_batch: int = 0, max_device_bytes: int = 0):
+        cfg = ServeConfig(device, max_device_bytes, max_len, max_queue, max_batch)
+        self._h = ctypes.c_void_p()
+        check(lib().trioseq_serve_create(ctypes.byref(cfg), ctypes.byref(sc or _default_scoring()),
+                                         ctypes.byref(self._h)))
+
+    def submit(self, triplet) -> int:
+        keep: list = []
+        tr = _triplet(triplet, keep)
+        rid = ctypes.c_uint64()
+        check(lib().trioseq_serve_submit(self._h, ctypes.byref(tr), ctypes.byref(rid)))
+        return int(rid.value)
+
+    @staticmethod
+    def _res(r: Result) -> dict:
+        return {"id": int(r.id), "score": int(r.score), "status": int(r.status),
+                "t_submit_ns": int(r.t_submit_ns), "t_done_ns": int(r.t_done_ns)}
+
+    def poll(self, cap: int = 4096) -> list:
+        buf = (Result * cap)()
+        n = ctypes.c_size_t()
+        check(lib().trioseq_serve_poll(self._h, buf, cap, ctypes.byref(n)))
+        return [self._res(buf[k]) for k in range(n.value)]
+
+    def wait(self, rid: int, timeout_s: float | None = None) -> dict:
+        r = Result()
+        t = -1 if timeout_s is None else int(timeout_s * 1e9)
+        check(lib().trioseq_serve_wait(self._h, rid, ctypes.byref(r), t))
+        return self._res(r)
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        check(lib().trioseq_serve_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServeStats._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            check(lib().trioseq_serve_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

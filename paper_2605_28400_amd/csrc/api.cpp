@@ -96,6 +96,10 @@ DevScoring make_dev_scoring(const trioseq_scoring& sc) {
   return d;
 }
 
+// Triplets with at least this many cells are split into panel jobs when the
+// plan picks engines itself (one wave on 2.5e8 cells takes ~0.1 s).
+const double kSplitCells = 2.5e8;
+
 uint64_t panel_steps(const uint32_t l[3], const KernelShape& ks) {
   const uint64_t pj = l[1] / (uint32_t)panel_rows(ks) + 1;
   const uint64_t pk = l[2] / (uint32_t)panel_cols(ks) + 1;
@@ -135,6 +139,50 @@ AxisChoice choose_axes_wide(const uint32_t len[3]) {
   return best;
 }
 
+uint64_t boundary_ints(const KernelShape& ks, uint32_t max_n0) {
+  const uint64_t rows = face_rows(max_n0);
+  return 3 * (2 * rows * panel_cols(ks) + rows * right_face_row(ks));  // plain + tagged
+}
+
+Boundary carve_boundary(const KernelShape& ks, uint32_t max_n0, int* q) {
+  const uint64_t rows = face_rows(max_n0);
+  const uint64_t top = rows * panel_cols(ks), left = rows * right_face_row(ks);
+  Boundary b;
+  b.plain[0] = q;
+  b.plain[1] = q + top;
+  b.plain[2] = q + 2 * top;
+  q += 2 * top + left;
+  b.tagged[0] = q;
+  b.tagged[1] = q + 2 * top;
+  b.tagged[2] = q + 4 * top;
+  b.rows = (uint32_t)rows;
+  return b;
+}
+
+SweepArgs make_sweep_args(const uint32_t* words, const TripletDesc* desc, const JobDesc* jobs,
+                          uint32_t njobs, uint32_t lds_n0, int32_t* scores, int* counter, int* ctl,
+                          int* face, uint64_t face_stride, int* pface, const Boundary& bnd,
+                          const DevScoring& sc) {
+  SweepArgs a;
+  a.words = words;
+  a.desc = desc;
+  a.jobs = jobs;
+  a.njobs = njobs;
+  a.lds_n0 = lds_n0;
+  a.scores = scores;
+  a.counter = counter;
+  a.ctl = ctl;
+  a.face = face;
+  a.face_stride = face_stride;
+  a.pface = pface;
+  for (int k = 0; k < 3; ++k) {
+    a.bnd_plain[k] = bnd.plain[k];
+    a.bnd_tagged[k] = bnd.tagged[k];
+  }
+  a.sc = sc;
+  return a;
+}
+
 trioseq_status device_props(DeviceProps* p) {
   TRIOSEQ_HIP(hipGetDevice(&p->device), "hipGetDevice");
   TRIOSEQ_HIP(hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device),
@@ -152,26 +200,23 @@ using namespace trioseq;
 struct trioseq_plan {
   int device = 0;
   size_t n = 0;
-  int engine = 0;
-  uint32_t lds_n0 = 0;
-  KernelShape ks{4, 4};
+  int engine = 0;  // 0: all triplets whole, 1: all split into panel jobs, 2: mixed
+  int modes = 1;   // kernel variant: bit 0 whole-triplet jobs, bit 1 panel jobs
+  KernelShape ks{4, 4, 4};
   int grid = 0, waves_per_cu = 0, panels = 0;
+  uint32_t njobs = 0, lds_n0 = 0;
   DevScoring sc{};
   double cells = 0;
   uint64_t workspace_bytes = 0;
-  // batch engine
   TripletDesc* d_desc = nullptr;
-  int* d_counter = nullptr;
+  JobDesc* d_jobs = nullptr;
+  int* d_counter = nullptr;  // job queue head
+  int* d_ctl = nullptr;      // [0] generation, [1] error flag
+  int* d_face = nullptr;     // per-wave workspace of whole-triplet jobs
   uint64_t face_stride = 0;
-  // wide engine
-  TripletDesc wide_desc{};
-  uint32_t* d_order = nullptr;
-  int* d_progress = nullptr;
-  uint32_t ppw = 0, pk_count = 0;
-  int* d_face = nullptr;
-  // sentinel faces for edge panels
+  int* d_pface = nullptr;    // panel-face pool of split triplets
+  int* d_bnd = nullptr;      // sentinel faces
   Boundary bnd{};
-  int* d_bnd = nullptr;
   // graph replay
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
@@ -187,10 +232,11 @@ static void plan_free(trioseq_plan* p) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   (void)hipFree(p->d_desc);
+  (void)hipFree(p->d_jobs);
   (void)hipFree(p->d_counter);
-  (void)hipFree(p->d_order);
-  (void)hipFree(p->d_progress);
+  (void)hipFree(p->d_ctl);
   (void)hipFree(p->d_face);
+  (void)hipFree(p->d_pface);
   (void)hipFree(p->d_bnd);
   delete p;
 }
@@ -240,24 +286,22 @@ trioseq_status trioseq_packed_layout(const uint32_t* lens, size_t n, uint64_t* w
   return TRIOSEQ_OK;
 }
 
-trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_off, size_t n,
-                                   const trioseq_scoring* scp, const trioseq_plan_options* opts,
-                                   trioseq_plan** out) {
-  if (!out) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: plan output is NULL");
-  if (n && !lens) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: lens is NULL");
-  if (n > (size_t)INT32_MAX) return fail(TRIOSEQ_ERR_TOO_LARGE, "plan_create: too many triplets");
-  trioseq_status st = validate_scoring(scp);
-  if (st != TRIOSEQ_OK) return st;
-  trioseq_plan_options o{-1, 0, 0, 0, 0};
-  if (opts) o = *opts;
-  if (o.engine < -1 || o.engine > 1) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: bad engine");
-  KernelShape ks{o.tile_rows ? o.tile_rows : 4, o.tile_cols ? o.tile_cols : 4};
-  if (!shape_supported(ks)) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: unsupported tile shape");
-  if (o.grid < 0) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: negative grid");
+}  // extern "C"
 
-  // Validate every triplet before touching the device.
+namespace trioseq {
+
+trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
+                            const trioseq_scoring& sc, const trioseq_plan_options& o, Layout* L) {
+  if (n && !lens) return fail(TRIOSEQ_ERR_INVALID_ARG, "lens is NULL");
+  if (n > (size_t)INT32_MAX) return fail(TRIOSEQ_ERR_TOO_LARGE, "too many triplets");
+  trioseq_status st = validate_scoring(&sc);
+  if (st != TRIOSEQ_OK) return st;
+  if (o.engine < -1 || o.engine > 1) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: bad engine");
+  if (o.grid < 0) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: negative grid");
+  KernelShape ks{o.tile_rows ? o.tile_rows : 4, o.tile_cols ? o.tile_cols : 4,
+                 o.waves_per_simd ? o.waves_per_simd : 2};
+  if (!shape_supported(ks)) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: unsupported tile shape");
   std::vector<uint64_t> offs;
-  const uint64_t* off = word_off;
   if (!off) {
     offs.resize(3 * n);
     uint64_t tw = 0;
@@ -271,11 +315,108 @@ trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_of
       return fail(TRIOSEQ_ERR_TOO_LARGE, "triplet " + std::to_string(t) +
                                              ": every sequence exceeds " +
                                              std::to_string(kMaxSweepLen) + " residues");
-    st = check_range(*scp, l[0], l[1], l[2], t);
+    st = check_range(sc, l[0], l[1], l[2], t);
     if (st != TRIOSEQ_OK) return st;
     cells += (double)l[0] * (double)l[1] * (double)l[2];
   }
+  const int H = panel_rows(ks), W = panel_cols(ks), RR = (int)right_face_row(ks);
 
+  // Which triplets are split into panel jobs: forced by the engine option,
+  // else a lone triplet (so it can use the whole GPU) and very large ones
+  // (one wave would take too long on them).
+  L->desc.assign(n, TripletDesc{});
+  std::vector<char> split(n, 0);
+  std::vector<uint64_t> cost(n, 0);
+  uint64_t stride = 0, pool = 0;
+  uint32_t max_n0 = 0;
+  int n_split = 0, panels = 0;
+  for (size_t t = 0; t < n; ++t) {
+    const uint32_t* l = lens + 3 * t;
+    const double c = (double)l[0] * l[1] * l[2];
+    const bool sp = o.engine == 1 || (o.engine == -1 && (n == 1 || c >= kSplitCells));
+    AxisChoice ax = sp ? choose_axes_wide(l) : choose_axes_batch(l, ks);
+    TripletDesc& d = L->desc[t];
+    for (int a = 0; a < 3; ++a) {
+      d.off[a] = off[3 * t + ax.perm[a]];
+      d.len[a] = l[ax.perm[a]];
+    }
+    d.out = (uint32_t)t;
+    d.face_off = 0;
+    const uint64_t rows = face_rows(d.len[0]);
+    const uint64_t PJ = d.len[1] / H + 1, PK = d.len[2] / W + 1;
+    if (sp && PJ * PK > 1) {
+      split[t] = 1;
+      ++n_split;
+      d.face_off = pool;
+      pool += PJ * PK * rows * (uint64_t)(W + RR) * 2;
+      panels += (int)(PJ * PK);
+    } else {
+      stride = std::max(stride, rows * (PK * W + RR));
+    }
+    cost[t] = panel_steps(d.len, ks);
+    max_n0 = std::max(max_n0, d.len[0]);
+  }
+  L->engine = n_split == 0 ? 0 : (n_split == (int)n ? 1 : 2);
+  L->modes = n_split == 0 ? 1 : (n_split == (int)n ? 2 : 3);
+  // Whole-triplet-only plans fit four waves per SIMD without much spilling
+  // on 4x4 tiles; panel jobs carry tag registers and use the two-wave budget.
+  if (!o.waves_per_simd && L->modes == 1 && ks.rj * ks.rk <= 16) {
+    KernelShape k4 = ks;
+    k4.wpe = 4;
+    if (shape_supported(k4)) ks = k4;
+  }
+  L->ks = ks;
+  L->panels = panels;
+  L->lds_n0 = max_n0;
+  L->cells = cells;
+  L->face_stride = (stride + 63) / 64 * 64;
+  L->pool_ints = pool;
+
+  // Job order: split triplets first (largest first, each panel after the
+  // panels it reads from: anti-diagonal order), then whole triplets longest
+  // first so the queue drains with short ones.
+  std::vector<size_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  L->jobs.clear();
+  L->jobs.reserve(n + panels);
+  for (size_t t : idx) {
+    if (!split[t]) continue;
+    const uint32_t PJ = L->desc[t].len[1] / H + 1, PK = L->desc[t].len[2] / W + 1;
+    for (uint32_t d = 0; d + 1 < PJ + PK; ++d)
+      for (uint32_t pj = (d >= PK ? d - PK + 1 : 0); pj <= std::min(d, PJ - 1); ++pj)
+        L->jobs.push_back(JobDesc{(uint32_t)t, pj * PK + (d - pj)});
+  }
+  for (size_t t : idx)
+    if (!split[t]) L->jobs.push_back(JobDesc{(uint32_t)t, kWholeTriplet});
+  return TRIOSEQ_OK;
+}
+
+trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested, int* grid,
+                           int* waves_per_cu) {
+  int w = 0;
+  TRIOSEQ_HIP(sweep_occupancy(L.ks, L.modes, L.lds_n0, &w), "occupancy");
+  int g = requested ? requested : dp.cus * std::max(1, w);
+  g = (int)std::min<size_t>((size_t)g, std::max<size_t>(L.jobs.size(), 1));
+  *grid = g;
+  *waves_per_cu = w;
+  return TRIOSEQ_OK;
+}
+
+}  // namespace trioseq
+
+extern "C" {
+
+trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_off, size_t n,
+                                   const trioseq_scoring* scp, const trioseq_plan_options* opts,
+                                   trioseq_plan** out) {
+  if (!out) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: plan output is NULL");
+  if (!scp) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: scoring is NULL");
+  trioseq_plan_options o{-1, 0, 0, 0, 0, 0};
+  if (opts) o = *opts;
+  Layout L;
+  trioseq_status st = build_layout(lens, word_off, n, *scp, o, &L);
+  if (st != TRIOSEQ_OK) return st;
   DeviceProps dp;
   st = device_props(&dp);
   if (st != TRIOSEQ_OK) return st;
@@ -284,129 +425,61 @@ trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_of
   if (!p) return fail(TRIOSEQ_ERR_NOMEM, "plan: host allocation");
   p->device = dp.device;
   p->n = n;
-  p->ks = ks;
+  p->ks = L.ks;
+  p->modes = L.modes;
+  p->engine = L.engine;
+  p->panels = L.panels;
+  p->lds_n0 = L.lds_n0;
+  p->njobs = (uint32_t)L.jobs.size();
   p->sc = make_dev_scoring(*scp);
-  p->cells = cells;
+  p->cells = L.cells;
   p->use_graph = o.use_graph != 0;
-  int engine = o.engine;
-  if (engine < 0) engine = (n == 1) ? 1 : 0;
-  p->engine = engine;
-
-  auto bail = [&](trioseq_status s) {
-    plan_free(p);
-    return s;
-  };
+  p->face_stride = L.face_stride;
   auto hip_bail = [&](hipError_t e, const char* what) {
     fail_hip(e, what);
-    trioseq_status s = (e == hipErrorOutOfMemory) ? TRIOSEQ_ERR_NOMEM : TRIOSEQ_ERR_DEVICE;
+    trioseq_status s2 = (e == hipErrorOutOfMemory) ? TRIOSEQ_ERR_NOMEM : TRIOSEQ_ERR_DEVICE;
     plan_free(p);
-    return s;
+    return s2;
   };
+  st = layout_grid(L, dp, o.grid, &p->grid, &p->waves_per_cu);
+  if (st != TRIOSEQ_OK) {
+    plan_free(p);
+    return st;
+  }
   hipError_t e;
-  const int H = panel_rows(ks), W = panel_cols(ks);
-
-  if (engine == 0) {
-    std::vector<TripletDesc> desc(n);
-    std::vector<uint64_t> cost(n);
-    uint64_t stride = 0;
-    uint32_t max_n0 = 0;
-    for (size_t t = 0; t < n; ++t) {
-      const uint32_t* l = lens + 3 * t;
-      AxisChoice ax = choose_axes_batch(l, ks);
-      TripletDesc& d = desc[t];
-      for (int a = 0; a < 3; ++a) {
-        d.off[a] = off[3 * t + ax.perm[a]];
-        d.len[a] = l[ax.perm[a]];
-      }
-      d.out = (uint32_t)t;
-      cost[t] = panel_steps(d.len, ks);
-      const uint64_t pk = d.len[2] / W + 1;
-      const uint64_t need = (uint64_t)face_rows(d.len[0]) * (pk * W + right_face_row(ks));
-      stride = std::max(stride, need);
-      max_n0 = std::max(max_n0, d.len[0]);
-    }
-    // Longest first: the persistent queue then ends with short triplets.
-    std::vector<size_t> idx(n);
-    std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<TripletDesc> sorted(n);
-    for (size_t q = 0; q < n; ++q) sorted[q] = desc[idx[q]];
-    stride = (stride + 63) / 64 * 64;
-    p->face_stride = stride;
-    p->lds_n0 = max_n0;
-    if ((e = batch_occupancy(ks, max_n0, &p->waves_per_cu)) != hipSuccess) return hip_bail(e, "occupancy");
-    int grid = o.grid ? o.grid : dp.cus * std::max(1, p->waves_per_cu);
-    grid = (int)std::min<size_t>((size_t)grid, std::max<size_t>(n, 1));
-    p->grid = grid;
-    const uint64_t face_bytes = (uint64_t)grid * stride * sizeof(int);
-    p->workspace_bytes = face_bytes + n * sizeof(TripletDesc) + 256;
-    if ((e = hipMalloc((void**)&p->d_counter, 256)) != hipSuccess) return hip_bail(e, "hipMalloc");
-    if (n) {
-      if ((e = hipMalloc((void**)&p->d_desc, n * sizeof(TripletDesc))) != hipSuccess)
-        return hip_bail(e, "hipMalloc desc");
-      if ((e = hipMemcpy(p->d_desc, sorted.data(), n * sizeof(TripletDesc), hipMemcpyHostToDevice)) !=
-          hipSuccess)
-        return hip_bail(e, "hipMemcpy desc");
-    }
-    if (face_bytes && (e = hipMalloc((void**)&p->d_face, face_bytes)) != hipSuccess)
-      return hip_bail(e, "hipMalloc face workspace");
-  } else {
-    if (n != 1) return bail(fail(TRIOSEQ_ERR_INVALID_ARG, "wide engine takes exactly one triplet"));
-    AxisChoice ax = choose_axes_wide(lens);
-    TripletDesc& d = p->wide_desc;
-    for (int a = 0; a < 3; ++a) {
-      d.off[a] = off[ax.perm[a]];
-      d.len[a] = lens[ax.perm[a]];
-    }
-    d.out = 0;
-    const uint32_t PJ = d.len[1] / H + 1, PK = d.len[2] / W + 1;
-    const uint32_t panels = PJ * PK;
-    p->panels = (int)panels;
-    p->pk_count = PK;
-    p->lds_n0 = d.len[0];
-    if ((e = wide_occupancy(ks, d.len[0], &p->waves_per_cu)) != hipSuccess) return hip_bail(e, "occupancy");
-    // Every wavefront must be resident at once: a panel waits on its
-    // neighbours' progress counters.
-    int cap = dp.cus * std::max(1, p->waves_per_cu);
-    int grid = o.grid ? std::min(o.grid, cap) : cap;
-    grid = (int)std::min<uint32_t>((uint32_t)grid, panels);
-    p->grid = grid;
-    p->ppw = (panels + grid - 1) / grid;
-    // Panels in order of their anti-diagonal pj + pk, dealt round-robin, so
-    // every wavefront visits its panels in dependency order.
-    std::vector<uint32_t> diag(panels);
-    std::iota(diag.begin(), diag.end(), 0u);
-    std::stable_sort(diag.begin(), diag.end(), [&](uint32_t a, uint32_t b) {
-      return (a / PK + a % PK) < (b / PK + b % PK);
-    });
-    std::vector<uint32_t> order((size_t)grid * p->ppw, 0xFFFFFFFFu);
-    for (uint32_t q = 0; q < panels; ++q) order[(size_t)(q % grid) * p->ppw + q / grid] = diag[q];
-    const uint64_t per_panel = (uint64_t)face_rows(d.len[0]) * (W + right_face_row(ks));
-    const uint64_t face_bytes = per_panel * panels * sizeof(int);
-    p->workspace_bytes = face_bytes + order.size() * 4 + panels * 4;
-    if ((e = hipMalloc((void**)&p->d_order, order.size() * 4)) != hipSuccess)
-      return hip_bail(e, "hipMalloc order");
-    if ((e = hipMemcpy(p->d_order, order.data(), order.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
-      return hip_bail(e, "hipMemcpy order");
-    if ((e = hipMalloc((void**)&p->d_progress, (panels + 1) * 4)) != hipSuccess)
-      return hip_bail(e, "hipMalloc progress");
-    if ((e = hipMalloc((void**)&p->d_face, face_bytes)) != hipSuccess)
-      return hip_bail(e, "hipMalloc face workspace");
+  const uint64_t face_bytes = (uint64_t)p->grid * L.face_stride * sizeof(int);
+  const uint64_t pool_bytes = L.pool_ints * sizeof(int);
+  if ((e = hipMalloc((void**)&p->d_counter, 256)) != hipSuccess) return hip_bail(e, "hipMalloc");
+  if ((e = hipMalloc((void**)&p->d_ctl, 256)) != hipSuccess) return hip_bail(e, "hipMalloc");
+  if ((e = hipMemset(p->d_ctl, 0, 256)) != hipSuccess) return hip_bail(e, "hipMemset");
+  if (n) {
+    if ((e = hipMalloc((void**)&p->d_desc, n * sizeof(TripletDesc))) != hipSuccess)
+      return hip_bail(e, "hipMalloc desc");
+    if ((e = hipMemcpy(p->d_desc, L.desc.data(), n * sizeof(TripletDesc), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return hip_bail(e, "hipMemcpy desc");
+    if ((e = hipMalloc((void**)&p->d_jobs, L.jobs.size() * sizeof(JobDesc))) != hipSuccess)
+      return hip_bail(e, "hipMalloc jobs");
+    if ((e = hipMemcpy(p->d_jobs, L.jobs.data(), L.jobs.size() * sizeof(JobDesc),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_bail(e, "hipMemcpy jobs");
   }
-  {
-    // Sentinel faces for panels on the tensor edge, built once per plan.
-    const uint64_t rows = face_rows(p->lds_n0);
-    const uint64_t top_ints = rows * W, left_ints = rows * right_face_row(ks);
-    const uint64_t bytes = (2 * top_ints + left_ints) * sizeof(int);
-    if ((e = hipMalloc((void**)&p->d_bnd, bytes)) != hipSuccess) return hip_bail(e, "hipMalloc boundary");
-    p->bnd.top_seed = p->d_bnd;
-    p->bnd.top = p->d_bnd + top_ints;
-    p->bnd.left = p->d_bnd + 2 * top_ints;
-    p->bnd.rows = (uint32_t)rows;
-    p->workspace_bytes += bytes;
-    if ((e = launch_init_boundary(ks, p->bnd, nullptr)) != hipSuccess) return hip_bail(e, "boundary init");
-    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_bail(e, "boundary init");
+  if (face_bytes && (e = hipMalloc((void**)&p->d_face, face_bytes)) != hipSuccess)
+    return hip_bail(e, "hipMalloc face workspace");
+  if (pool_bytes) {
+    // Tagged faces start at tag 0, which no run uses, so nothing stale matches.
+    if ((e = hipMalloc((void**)&p->d_pface, pool_bytes)) != hipSuccess)
+      return hip_bail(e, "hipMalloc panel faces");
+    if ((e = hipMemset(p->d_pface, 0, pool_bytes)) != hipSuccess) return hip_bail(e, "hipMemset");
   }
+  const uint64_t bnd_ints = boundary_ints(L.ks, L.lds_n0);
+  if ((e = hipMalloc((void**)&p->d_bnd, bnd_ints * sizeof(int))) != hipSuccess)
+    return hip_bail(e, "hipMalloc boundary");
+  p->bnd = carve_boundary(L.ks, L.lds_n0, p->d_bnd);
+  if ((e = launch_init_boundary(L.ks, p->bnd, nullptr)) != hipSuccess) return hip_bail(e, "boundary init");
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_bail(e, "boundary init");
+  p->workspace_bytes = face_bytes + pool_bytes + bnd_ints * sizeof(int) +
+                       n * sizeof(TripletDesc) + L.jobs.size() * sizeof(JobDesc) + 512;
   if (p->use_graph) {
     if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
       return hip_bail(e, "hipStreamCreate");
@@ -417,41 +490,13 @@ trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_of
 
 static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t* d_scores,
                                hipStream_t s) {
+  if (p->n == 0) return hipSuccess;
   hipError_t e;
-  if (p->engine == 0) {
-    if (p->n == 0) return hipSuccess;
-    if ((e = launch_reset(p->d_counter, 1, s)) != hipSuccess) return e;
-    BatchArgs a;
-    a.words = d_words;
-    a.desc = p->d_desc;
-    a.scores = d_scores;
-    a.counter = p->d_counter;
-    a.face = p->d_face;
-    a.face_stride = p->face_stride;
-    a.n = (uint32_t)p->n;
-    a.lds_n0 = p->lds_n0;
-    a.bnd_top_seed = p->bnd.top_seed;
-    a.bnd_top = p->bnd.top;
-    a.bnd_left = p->bnd.left;
-    a.sc = p->sc;
-    return launch_batch(p->ks, a, p->grid, s);
-  }
-  if ((e = launch_reset(p->d_progress, p->panels + 1, s)) != hipSuccess) return e;
-  WideArgs a;
-  a.words = d_words;
-  a.desc = p->wide_desc;
-  a.scores = d_scores;
-  a.face = p->d_face;
-  a.progress = p->d_progress;
-  a.order = p->d_order;
-  a.panels_per_wave = p->ppw;
-  a.n_panels = (uint32_t)p->panels;
-  a.pk_count = p->pk_count;
-  a.bnd_top_seed = p->bnd.top_seed;
-  a.bnd_top = p->bnd.top;
-  a.bnd_left = p->bnd.left;
-  a.sc = p->sc;
-  return launch_wide(p->ks, a, p->grid, s);
+  if ((e = launch_prepare(p->d_ctl, p->d_counter, s)) != hipSuccess) return e;
+  SweepArgs a = make_sweep_args(d_words, p->d_desc, p->d_jobs, p->njobs, p->lds_n0, d_scores,
+                                p->d_counter, p->d_ctl, p->d_face, p->face_stride, p->d_pface,
+                                p->bnd, p->sc);
+  return launch_sweep(p->ks, p->modes, a, p->grid, s);
 }
 
 trioseq_status trioseq_plan_run(trioseq_plan* p, const uint32_t* d_words, int32_t* d_scores,
@@ -541,7 +586,7 @@ static trioseq_status run_host_batch(const trioseq_triplet* t, size_t n, const t
   st = pack_triplets(t, n, &lens, &offs, &words);
   if (st != TRIOSEQ_OK) return st;
   if (n == 0) return TRIOSEQ_OK;
-  trioseq_plan_options o{engine, 0, 0, 0, 0};
+  trioseq_plan_options o{engine, 0, 0, 0, 0, 0};
   trioseq_plan* plan = nullptr;
   st = trioseq_plan_create(lens.data(), offs.data(), n, sc, &o, &plan);
   if (st != TRIOSEQ_OK) return st;

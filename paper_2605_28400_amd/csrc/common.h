@@ -35,6 +35,7 @@ struct AxisChoice {
 AxisChoice choose_axes_batch(const uint32_t len[3], const KernelShape& ks);
 AxisChoice choose_axes_wide(const uint32_t len[3]);
 uint64_t panel_steps(const uint32_t len_axis[3], const KernelShape& ks);
+extern const double kSplitCells;
 
 struct DeviceProps {
   int device;
@@ -44,5 +45,36 @@ struct DeviceProps {
 trioseq_status device_props(DeviceProps* p);
 
 uint64_t now_ns();
+
+// Sentinel-face buffers for sweeps up to max_n0 (plain + tagged layouts).
+uint64_t boundary_ints(const KernelShape& ks, uint32_t max_n0);
+Boundary carve_boundary(const KernelShape& ks, uint32_t max_n0, int* base);
+SweepArgs make_sweep_args(const uint32_t* words, const TripletDesc* desc, const JobDesc* jobs,
+                          uint32_t njobs, uint32_t lds_n0, int32_t* scores, int* counter, int* ctl,
+                          int* face, uint64_t face_stride, int* pface, const Boundary& bnd,
+                          const DevScoring& sc);
+
+// Host-side plan of one batch: validation, per-triplet axis choice, the job
+// queue in dependency order, and the device memory the sweep needs.
+struct Layout {
+  KernelShape ks{4, 4, 2};
+  int modes = 1;   // bit 0 whole-triplet jobs, bit 1 panel jobs
+  int engine = 0;  // 0 all whole, 1 all split, 2 mixed
+  int panels = 0;
+  uint32_t lds_n0 = 0;
+  double cells = 0;
+  std::vector<TripletDesc> desc;
+  std::vector<JobDesc> jobs;
+  uint64_t face_stride = 0;  // ints of whole-triplet workspace per wave
+  uint64_t pool_ints = 0;    // ints of panel faces of split triplets
+};
+
+// Validates and lays out n triplets (lens[3t+s], word offsets off[3t+s]).
+// Touches no device state.
+trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
+                            const trioseq_scoring& sc, const trioseq_plan_options& o, Layout* L);
+// Waves to launch for a layout on this device.
+trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested, int* grid,
+                           int* waves_per_cu);
 
 }  // namespace trioseq

@@ -43,61 +43,58 @@ struct DevScoring {
 // One triplet as the kernels see it: the three sequences already assigned
 // to the sweep axis (0), the row axis (1) and the column axis (2).
 struct TripletDesc {
-  uint64_t off[3];  // word offsets of the three sequences in the word array
-  uint32_t len[3];  // lengths on the sweep, row and column axes
-  uint32_t out;     // index of this triplet's score in the caller's output
+  uint64_t off[3];    // word offsets of the three sequences in the word array
+  uint32_t len[3];    // lengths on the sweep, row and column axes
+  uint32_t out;       // index of this triplet's score in the caller's output
+  uint64_t face_off;  // split triplets: ints from the panel-face pool base
 };
 
-// Sentinel faces for edge panels (rows = face_rows of the longest sweep).
+// A queue entry: one triplet swept whole by one wave, or one panel of a
+// split triplet (panel = pj * PK + pk).
+constexpr uint32_t kWholeTriplet = 0xFFFFFFFFu;
+struct JobDesc {
+  uint32_t trip;
+  uint32_t panel;
+};
+
+// Sentinel faces for edge panels (rows = face_rows of the longest sweep):
+// [0] top with the seed at slice 0, k = 0; [1] top; [2] left. plain: one
+// int per entry (whole-triplet jobs); tagged: (value, tag) per entry.
 struct Boundary {
-  int* top_seed;  // rows x panel_cols, with the seed at slice 0, k = 0
-  int* top;       // rows x panel_cols
-  int* left;      // rows x right_face_row
+  int* plain[3];
+  int* tagged[3];
   uint32_t rows;
 };
 
-struct BatchArgs {
-  uint32_t lds_n0;          // longest sweep length the dynamic LDS was sized for
+struct SweepArgs {
   const uint32_t* words;
-  const TripletDesc* desc;  // in processing (LPT) order
+  const TripletDesc* desc;
+  const JobDesc* jobs;
+  uint32_t njobs;
+  uint32_t lds_n0;      // longest sweep length the dynamic LDS was sized for
   int32_t* scores;
-  int* counter;             // work queue head, zeroed before each launch
-  int* face;                // per-wave workspace
-  uint64_t face_stride;     // ints of workspace per wave
-  uint32_t n;
-  const int* bnd_top_seed;
-  const int* bnd_top;
-  const int* bnd_left;
-  DevScoring sc;
-};
-
-struct WideArgs {
-  const uint32_t* words;
-  TripletDesc desc;
-  int32_t* scores;
-  int* face;          // per-panel face buffers
-  int* progress;      // per-panel completed-step counters + 1 error flag, zeroed before launch
-  const uint32_t* order;  // panel ids (pj * PK + pk) in wave-major order
-  uint32_t panels_per_wave;
-  uint32_t n_panels;
-  uint32_t pk_count;
-  const int* bnd_top_seed;
-  const int* bnd_top;
-  const int* bnd_left;
+  int* counter;         // job queue head (zeroed by k_prepare)
+  int* ctl;             // [0] run generation, [1] error flag
+  int* face;            // per-wave workspace for whole-triplet jobs
+  uint64_t face_stride; // ints per wave
+  int* pface;           // panel-face pool of split triplets
+  const int* bnd_plain[3];
+  const int* bnd_tagged[3];
   DevScoring sc;
 };
 
 struct KernelShape {
   int rj, rk;  // lane tile (rows x columns)
+  int wpe;     // waves per SIMD the register budget is sized for
 };
 
 // Launchers (sweep.hip).
-hipError_t launch_reset(int* p, int n, hipStream_t s);
 hipError_t launch_init_boundary(const KernelShape& ks, const Boundary& b, hipStream_t s);
-hipError_t launch_batch(const KernelShape& ks, const BatchArgs& a, int grid, hipStream_t s);
-hipError_t launch_wide(const KernelShape& ks, const WideArgs& a, int grid, hipStream_t s);
-hipError_t batch_occupancy(const KernelShape& ks, uint32_t lds_n0, int* waves_per_cu);
-hipError_t wide_occupancy(const KernelShape& ks, uint32_t lds_n0, int* waves_per_cu);
+hipError_t launch_prepare(int* ctl, int* counter, hipStream_t s);
+// modes: bit 0 = whole-triplet jobs present, bit 1 = panel jobs present.
+hipError_t launch_sweep(const KernelShape& ks, int modes, const SweepArgs& a, int grid,
+                        hipStream_t s);
+hipError_t sweep_occupancy(const KernelShape& ks, int modes, uint32_t lds_n0, int* waves_per_cu);
 bool shape_supported(const KernelShape& ks);
 
 inline int panel_rows(const KernelShape& ks) { return kGJ * ks.rj; }

@@ -37,11 +37,12 @@
 //    column 0 use a table whose bytes are -128 and C = kSent, and the
 //    virtual row above the tensor holds 0 at (i=0, k=0), which seeds
 //    M'(0,0,0) = 0. No special edge code exists.
-//  * Batched triplets: a persistent grid; each wavefront pops triplets
-//    (longest first) and sweeps their panels in order, reusing its face
-//    buffers in place. One large triplet: panels spread over many
-//    wavefronts, faces handed over through HBM under per-panel progress
-//    counters (release/acquire at agent scope).
+//  * One persistent kernel pops jobs from a device queue. A whole-triplet
+//    job sweeps all panels of a small triplet in the wave's own workspace
+//    (faces reused in place); a panel job sweeps one panel of a large
+//    triplet split over many waves, whose faces travel through HBM as
+//    (value, run-tag) pairs with device-coherent accesses (see the
+//    hand-over notes below).
 #include <type_traits>
 
 #include "internal.h"
@@ -96,47 +97,32 @@ struct PanelIO {
   int* bot;           // this panel's bottom face (nullptr: not needed)
   uint32_t bot_stride;
   int* right;         // this panel's right face (nullptr: not needed)
-  const int* top_prog;
-  const int* left_prog;
-  int* my_prog;
-  int* err;           // set when a progress wait gave up
+  int gen;            // run generation: wide-engine faces carry it as a tag
+  int* err;           // set when a tag wait gave up (wide engine)
 };
 
-// Cross-wavefront hand-over in the wide engine. Face values are written and
-// read with device-coherent buffer accesses (the SC1 cache-policy bit: the
-// same per-instruction coherence the compiler uses for relaxed agent-scope
-// atomics), so no cache-wide write-back or invalidate is ever needed. The
-// producer waits for its face stores to complete (s_waitcnt vmcnt(0)) before
-// it publishes the count of finished steps; the consumer polls that count.
+// Cross-wavefront hand-over in the wide engine. Every face entry is a
+// (value, tag) pair written by one 64-bit store, tag = the run's generation
+// number, so a consumer knows an entry is current without any flag or
+// fence: entries left from an earlier run carry an older tag. Faces are
+// written and read with device-coherent buffer accesses (the SC1
+// cache-policy bit, the per-instruction coherence that relaxed agent-scope
+// atomics use); producers never wait, and a consumer whose chunk of entries
+// is not complete yet re-reads the stale ones. Sentinel faces carry the tag
+// kTagAlways, valid in every run.
 constexpr int kCohNone = 0;
-constexpr int kCohDevice = 16;  // SC1
+constexpr int kCohDevice = 16;              // SC1
+constexpr int kVolatile = (int)(1u << 31);  // compiler-side: never merge or hoist the load
+constexpr int kTagAlways = 0x7FFFFFFF;
 
-// Bounded wait for a neighbour panel's progress counter. Every wave leaves
-// the loop: after kSpinLimit polls it raises the error flag and proceeds
-// (the score is then marked invalid), so a lost producer cannot hang the GPU.
-constexpr int kSpinLimit = 1 << 21;
+// Bound on the wait for a stale chunk, in ticks of the 100 MHz wall clock.
+// Every wave leaves the loop: past the limit it raises the error flag and
+// proceeds (the score is then marked invalid), so a lost producer cannot
+// hang the GPU.
+constexpr uint64_t kWaitTicks = 200000000ull;  // 2 s
 
-__device__ __forceinline__ void wait_progress(const int* prog, int need, int* err) {
-  if (threadIdx.x == 0) {
-    int spins = 0;
-    while (__hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-      if (++spins > kSpinLimit) {
-        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-  }
-  // Face loads must not be hoisted above the poll.
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-__device__ __forceinline__ void publish_progress(int* prog, int v) {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);  // every face store of this wave has completed
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  if (threadIdx.x == 0) __hip_atomic_store(prog, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v4i __attribute__((ext_vector_type(4)));
 
 // Per-slice lookup shifts: shb[i + kFacePre] = 8 * code(S0[i-1]) for slices
 // 1..n0, 0 elsewhere; covers slices -kFacePre .. n0 + 47.
@@ -160,6 +146,7 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
                             const PanelIO& io, int32_t* score_out) {
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
   constexpr int COH = WIDE ? kCohDevice : kCohNone;
+  constexpr int ES = WIDE ? 2 : 1;  // ints per face entry: value (+ tag)
   const int lane = threadIdx.x;
   const int y = lane >> 3, x = lane & 7;
   const int n0 = (int)td.len[0], n1 = (int)td.len[1], n2 = (int)td.len[2];
@@ -223,14 +210,16 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   // Face resources. Rows are padded (kFacePre before slice 0), so every
   // staging load and every edge store stays inside its buffer.
   const uint32_t frows = face_rows((uint32_t)n0);
-  const Rsrc r_top = make_rsrc(io.top, (uint64_t)frows * io.top_stride * 4);
-  const Rsrc r_left = make_rsrc(io.left, (uint64_t)frows * RR * 4);
+  const Rsrc r_top = make_rsrc(io.top, (uint64_t)frows * io.top_stride * 4 * ES);
+  const Rsrc r_left = make_rsrc(io.left, (uint64_t)frows * RR * 4 * ES);
   // An absent output gets an empty resource: its stores are all dropped.
   const Rsrc r_bot = make_rsrc(io.bot ? io.bot : io.top,
-                               io.bot ? (uint64_t)frows * io.bot_stride * 4 : 0);
+                               io.bot ? (uint64_t)frows * io.bot_stride * 4 * ES : 0);
   const Rsrc r_right = make_rsrc(io.right ? io.right : io.left,
-                                 io.right ? (uint64_t)frows * RR * 4 : 0);
-  const uint32_t ts = io.top_stride, bs = io.bot_stride;
+                                 io.right ? (uint64_t)frows * RR * 4 * ES : 0);
+  // Row strides in bytes.
+  const uint32_t ts = io.top_stride * 4u * ES, bs = io.bot_stride * 4u * ES;
+  constexpr uint32_t RRB = RR * 4u * ES;
 
   // Staging. Value q of a chunk is, for this lane, entry v = lane + 64 q of
   // one of three LDS rings (top face, corners, left face). Within a ring a
@@ -244,37 +233,102 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   constexpr int RT = 64 / W, RL = 64 / H;  // ring rows per q
   static_assert(64 % W == 0 && 64 % H == 0 && QC == 1, "ring widths must divide 64");
   const int eT = lane % W;
-  const uint32_t offT = (uint32_t)(((kFacePre + lane / W - eT / RK) * (int)ts + eT) * 4);
+  const uint32_t offT = (uint32_t)((kFacePre + lane / W - eT / RK) * (int)ts + eT * 4 * ES);
   const int eC = lane % kGK;
   const bool corner_from_left = eC == 0;
   const uint32_t offC = corner_from_left
-                            ? (uint32_t)((kFacePre + lane / kGK) * RR * 4)
-                            : (uint32_t)(((kFacePre + lane / kGK - eC) * (int)ts + eC * RK - 1) * 4);
+                            ? (uint32_t)((kFacePre + lane / kGK) * (int)RRB)
+                            : (uint32_t)((kFacePre + lane / kGK - eC) * (int)ts + (eC * RK - 1) * 4 * ES);
   const int eL = lane % H;
-  const uint32_t offL = (uint32_t)(((kFacePre + lane / H - eL / RJ) * RR + 4 + eL) * 4);
+  const uint32_t offL = (uint32_t)((kFacePre + lane / H - eL / RJ) * (int)RRB + (4 + eL) * 4 * ES);
+  // Slice of entry q in chunk c is c * kChunk + rel(q).
+  const int relT = lane / W - eT / RK, relC = lane / kGK - eC, relL = lane / H - eL / RJ;
+  auto rel_of = [&](int q) {
+    return q < QT ? relT + q * RT : q < QT + QC ? relC : relL + (q - QT - QC) * RL;
+  };
 
-  int pf[NPF];
-  auto stage_load = [&](int c) {
+  // Face entry q of chunk c for this lane: (value, tag); tag is unused in
+  // the batch engine. Re-reads of stale entries are volatile so that they
+  // really go to memory again instead of reusing the first load.
+  auto load_entry = [&](int q, int c, auto retry_tag) -> v2i {
+    constexpr int LDC = decltype(retry_tag)::value ? (COH | kVolatile) : COH;
     const uint32_t base = (uint32_t)(c * kChunk);
+    if (q < QT) {
+      const uint32_t so = (base + q * RT) * ts;
+      if (WIDE) return __builtin_amdgcn_raw_buffer_load_b64(r_top, offT, so, LDC);
+      return (v2i){(int)__builtin_amdgcn_raw_buffer_load_b32(r_top, offT, so, LDC), 0};
+    } else if (q < QT + QC) {
+      const uint32_t ot = corner_from_left ? kOob : offC, ol = corner_from_left ? offC : kOob;
+      if (WIDE)
+        return __builtin_amdgcn_raw_buffer_load_b64(r_top, ot, base * ts, LDC) |
+               __builtin_amdgcn_raw_buffer_load_b64(r_left, ol, base * RRB, LDC);
+      return (v2i){(int)(__builtin_amdgcn_raw_buffer_load_b32(r_top, ot, base * ts, LDC) |
+                         __builtin_amdgcn_raw_buffer_load_b32(r_left, ol, base * RRB, LDC)),
+                   0};
+    } else {
+      const uint32_t so = (base + (q - QT - QC) * RL) * RRB;
+      if (WIDE) return __builtin_amdgcn_raw_buffer_load_b64(r_left, offL, so, LDC);
+      return (v2i){(int)__builtin_amdgcn_raw_buffer_load_b32(r_left, offL, so, LDC), 0};
+    }
+  };
+  int pf[NPF], pt[NPF];
+  auto stage_load = [&](int c) {
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
-      int v;
-      if (q < QT) {
-        v = __builtin_amdgcn_raw_buffer_load_b32(r_top, offT, (base + q * RT) * ts * 4u, COH);
-      } else if (q < QT + QC) {
-        const int a = __builtin_amdgcn_raw_buffer_load_b32(r_top, corner_from_left ? kOob : offC,
-                                                           base * ts * 4u, COH);
-        const int b = __builtin_amdgcn_raw_buffer_load_b32(r_left, corner_from_left ? offC : kOob,
-                                                           base * RR * 4u, COH);
-        v = a | b;
-      } else {
-        v = __builtin_amdgcn_raw_buffer_load_b32(r_left, offL,
-                                                 (base + (q - QT - QC) * RL) * RR * 4u, COH);
+      const v2i e = load_entry(q, c, std::false_type());
+      pf[q] = e.x;
+      pt[q] = e.y;
+    }
+  };
+  // Wide engine: wait until every entry the sweep uses carries this run's
+  // tag. Entries of slices past n0 are never written by the producer (its
+  // drain stops earlier) and only feed cells past n0, so they are skipped.
+  // While the chunk is stale only two lanes poll, each one probe entry that
+  // its producer writes last for this chunk (slice min(c*kChunk+7, n0),
+  // entry 0), with a pause between polls; the whole chunk is re-read once
+  // both probes are current. Waiting waves thus put almost no load on the
+  // memory system the producers need.
+  const bool probe_top = lane == 0 && pj > 0, probe_left = lane == 1 && pk > 0;
+  auto stage_validate = [&](int c) {
+    if (!WIDE) return;
+    auto chunk_ok = [&]() {
+      bool ok = true;
+#pragma unroll
+      for (int q = 0; q < NPF; ++q) ok = ok && (pt[q] >= io.gen || c * kChunk + rel_of(q) > n0);
+      return __builtin_amdgcn_ballot_w64(!ok) == 0;
+    };
+    if (chunk_ok()) return;
+    const uint64_t t_start = wall_clock64();
+    const int ps = min(c * kChunk + kChunk - 1, n0);
+    const uint32_t probe_off = probe_top ? (uint32_t)((kFacePre + ps) * (int)ts)
+                                         : (uint32_t)((kFacePre + ps) * (int)RRB + 4 * 4 * ES);
+    for (;;) {
+      if (wall_clock64() - t_start > kWaitTicks) {
+        if (lane == 0) __hip_atomic_store(io.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
       }
-      pf[q] = v;
+      __builtin_amdgcn_s_sleep(16);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      bool probe_ok = true;
+      if (probe_top)
+        probe_ok = ((v2i)__builtin_amdgcn_raw_buffer_load_b64(r_top, probe_off, 0u,
+                                                              kCohDevice | kVolatile)).y >= io.gen;
+      if (probe_left)
+        probe_ok = ((v2i)__builtin_amdgcn_raw_buffer_load_b64(r_left, probe_off, 0u,
+                                                              kCohDevice | kVolatile)).y >= io.gen;
+      if (__builtin_amdgcn_ballot_w64(!probe_ok) != 0) continue;
+#pragma unroll
+      for (int q = 0; q < NPF; ++q)
+        if (pt[q] < io.gen && c * kChunk + rel_of(q) <= n0) {
+          const v2i e = load_entry(q, c, std::true_type());
+          pf[q] = e.x;
+          pt[q] = e.y;
+        }
+      if (chunk_ok()) break;
     }
   };
   auto stage_finish = [&](int c) {
+    stage_validate(c);
     const int rr = (c & 1) * kChunk;
     int* rt = &L.ringT[rr][0];
     int* rc = &L.ringC[rr][0];
@@ -290,11 +344,6 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
     }
   };
 
-  if (WIDE) {
-    const int need = min(2 * kChunk, stepsp);
-    if (io.top_prog) wait_progress(io.top_prog, need, io.err);
-    if (io.left_prog) wait_progress(io.left_prog, need, io.err);
-  }
   stage_load(0);
   // Before step 0 the neighbour slots hold slice "-1" for every lane: the
   // sentinel (they are read at step 0, before any lane has written them).
@@ -317,10 +366,10 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   // Edge stores: bottom row (y = 7), right column (x = 7), and the corner
   // for the next panel (lane (0,7)). The row of slice i is i + kFacePre.
   const uint32_t vo_bot =
-      (y == kGJ - 1) ? (uint32_t)(((kFacePre - y - x) * (int)bs + x * RK) * 4) : kOob;
+      (y == kGJ - 1) ? (uint32_t)((kFacePre - y - x) * (int)bs + x * RK * 4 * ES) : kOob;
   const uint32_t vo_right =
-      (x == kGK - 1) ? (uint32_t)(((kFacePre - y - x) * RR + 4 + y * RJ) * 4) : kOob;
-  const uint32_t vo_corner = (x == kGK - 1 && y == 0) ? (uint32_t)((kFacePre - x) * RR * 4) : kOob;
+      (x == kGK - 1) ? (uint32_t)((kFacePre - y - x) * (int)RRB + (4 + y * RJ) * 4 * ES) : kOob;
+  const uint32_t vo_corner = (x == kGK - 1 && y == 0) ? (uint32_t)((kFacePre - x) * (int)RRB) : kOob;
   const int sh_base = kFacePre - y - x;
 
   auto run_chunk = [&](int c, bool cap) {
@@ -373,19 +422,31 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
       L.sX[lane] = Lh[RJ - 1];
 
       // Edge stores (the hardware drops lanes whose offset is kOob).
+      if (WIDE) {
+        const int g = io.gen;
 #pragma unroll
-      for (int cc = 0; cc < RK; cc += 4)
-        __builtin_amdgcn_raw_buffer_store_b128(
-            (__attribute__((ext_vector_type(4))) int){N[RJ - 1][cc], N[RJ - 1][cc + 1],
-                                                     N[RJ - 1][cc + 2], N[RJ - 1][cc + 3]},
-            r_bot, vo_bot + cc * 4, (uint32_t)t * bs * 4u, COH);
+        for (int cc = 0; cc < RK; cc += 2)
+          __builtin_amdgcn_raw_buffer_store_b128((v4i){N[RJ - 1][cc], g, N[RJ - 1][cc + 1], g}, r_bot,
+                                                 vo_bot + cc * 8, (uint32_t)t * bs, COH);
 #pragma unroll
-      for (int r = 0; r < RJ; r += 4)
-        __builtin_amdgcn_raw_buffer_store_b128(
-            (__attribute__((ext_vector_type(4))) int){N[r][RK - 1], N[r + 1][RK - 1],
-                                                     N[r + 2][RK - 1], N[r + 3][RK - 1]},
-            r_right, vo_right + r * 4, (uint32_t)t * RR * 4u, COH);
-      __builtin_amdgcn_raw_buffer_store_b32(T[RK - 1], r_right, vo_corner, (uint32_t)t * RR * 4u, COH);
+        for (int r = 0; r < RJ; r += 2)
+          __builtin_amdgcn_raw_buffer_store_b128((v4i){N[r][RK - 1], g, N[r + 1][RK - 1], g}, r_right,
+                                                 vo_right + r * 8, (uint32_t)t * RRB, COH);
+        __builtin_amdgcn_raw_buffer_store_b64((v2i){T[RK - 1], g}, r_right, vo_corner,
+                                              (uint32_t)t * RRB, COH);
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < RK; cc += 4)
+          __builtin_amdgcn_raw_buffer_store_b128(
+              (v4i){N[RJ - 1][cc], N[RJ - 1][cc + 1], N[RJ - 1][cc + 2], N[RJ - 1][cc + 3]}, r_bot,
+              vo_bot + cc * 4, (uint32_t)t * bs, COH);
+#pragma unroll
+        for (int r = 0; r < RJ; r += 4)
+          __builtin_amdgcn_raw_buffer_store_b128(
+              (v4i){N[r][RK - 1], N[r + 1][RK - 1], N[r + 2][RK - 1], N[r + 3][RK - 1]}, r_right,
+              vo_right + r * 4, (uint32_t)t * RRB, COH);
+        __builtin_amdgcn_raw_buffer_store_b32(T[RK - 1], r_right, vo_corner, (uint32_t)t * RRB, COH);
+      }
 
       if (cap) {
         if (own && t - y - x == n0) {
@@ -410,120 +471,138 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   for (int c = 0; c < nchunks; ++c) {
     stage_finish(c);
     if (c + 1 < nchunks) {
-      if (WIDE) {
-        const int need = min((c + 3) * kChunk, stepsp);
-        if (io.top_prog) wait_progress(io.top_prog, need, io.err);
-        if (io.left_prog) wait_progress(io.left_prog, need, io.err);
-      }
       stage_load(c + 1);
     }
     const bool cap_chunk =
         score_out != nullptr && n0 >= c * kChunk - kSkew && n0 <= c * kChunk + kChunk - 1;
     run_chunk(c, cap_chunk);
-    if (WIDE && io.my_prog) publish_progress(io.my_prog, (c + 1) * kChunk);
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-  if (own) *score_out = L.cap[rsel * RK + csel] + sc.gap2 * (n0 + n1 + n2);
+  // System scope: the score may live in mapped host memory (serving), where
+  // the host picks it up while the kernel is still running.
+  if (own)
+    __hip_atomic_store(score_out, L.cap[rsel * RK + csel] + sc.gap2 * (n0 + n1 + n2),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-template <int RJ, int RK>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RJ * RK <= 16 ? 4 : 2))) k_batch(BatchArgs a) {
+// The persistent scoring kernel. Waves pop jobs from a device queue in
+// the order the host wrote them (every job after the jobs it depends on):
+//  * a whole-triplet job sweeps all panels of one triplet, in place, in the
+//    wave's own face workspace;
+//  * a panel job sweeps one panel of a split triplet; its faces live in the
+//    triplet's panel-face pool as (value, tag) entries and it waits for the
+//    entries of its upper and left neighbours. Those neighbours were popped
+//    earlier by waves that are running, so every wait ends no matter how many
+//    waves of the grid are resident.
+// MODES: bit 0 = the plan has whole-triplet jobs, bit 1 = panel jobs; a
+// kernel built for one kind only carries no registers for the other.
+template <int RJ, int RK, int WPE, int MODES>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) k_sweep(SweepArgs a) {
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
   __shared__ Lds<RJ, RK> L;
   extern __shared__ uint8_t shb[];
   int* face = a.face + (uint64_t)blockIdx.x * a.face_stride;
+  const int gen = __hip_atomic_load(a.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t staged = 0xFFFFFFFFu;
   for (;;) {
     if (threadIdx.x == 0) L.wsync = atomicAdd(a.counter, 1);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     const int idx = __builtin_amdgcn_readfirstlane(L.wsync);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-    if (idx >= (int)a.n) break;
-    const TripletDesc td = a.desc[idx];
-    stage_shifts(shb, a.words, td);
+    if (idx >= (int)a.njobs) break;
+    const JobDesc jd = a.jobs[idx];
+    const TripletDesc td = a.desc[jd.trip];
+    if (jd.trip != staged) {
+      stage_shifts(shb, a.words, td);
+      staged = jd.trip;
+    }
     const int n0 = (int)td.len[0], n1 = (int)td.len[1], n2 = (int)td.len[2];
     const int PJ = n1 / H + 1, PK = n2 / W + 1;
-    const uint32_t fr_rows = face_rows((uint32_t)n0);
-    int* fb = face;
-    int* fr = face + (uint64_t)fr_rows * (uint64_t)(PK * W);
-    for (int pj = 0; pj < PJ; ++pj) {
-      for (int pk = 0; pk < PK; ++pk) {
-        PanelIO io;
-        io.top = pj ? fb + pk * W : (pk ? a.bnd_top : a.bnd_top_seed);
-        io.top_stride = pj ? (uint32_t)(PK * W) : (uint32_t)W;
-        io.left = pk ? fr : a.bnd_left;
-        io.bot = pj + 1 < PJ ? fb + pk * W : nullptr;
-        io.bot_stride = (uint32_t)(PK * W);
-        io.right = pk + 1 < PK ? fr : nullptr;
-        io.top_prog = io.left_prog = nullptr;
-        io.my_prog = nullptr;
-        io.err = nullptr;
-        int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
-        sweep_panel<RJ, RK, false>(L, shb, a.sc, a.words, td, pj, pk, io, so);
+    const uint64_t rows = face_rows((uint32_t)n0);
+    if ((MODES & 1) && jd.panel == kWholeTriplet) {
+      int* fb = face;
+      int* fr = face + rows * (uint64_t)(PK * W);
+      for (int pj = 0; pj < PJ; ++pj) {
+        for (int pk = 0; pk < PK; ++pk) {
+          PanelIO io;
+          io.top = pj ? fb + pk * W : (pk ? a.bnd_plain[1] : a.bnd_plain[0]);
+          io.top_stride = pj ? (uint32_t)(PK * W) : (uint32_t)W;
+          io.left = pk ? fr : a.bnd_plain[2];
+          io.bot = pj + 1 < PJ ? fb + pk * W : nullptr;
+          io.bot_stride = (uint32_t)(PK * W);
+          io.right = pk + 1 < PK ? fr : nullptr;
+          io.gen = 0;
+          io.err = nullptr;
+          int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
+          sweep_panel<RJ, RK, false>(L, shb, a.sc, a.words, td, pj, pk, io, so);
+        }
       }
+    } else if (MODES & 2) {
+      const uint32_t p = jd.panel;
+      const int pj = (int)(p / (uint32_t)PK), pk = (int)(p % (uint32_t)PK);
+      const uint64_t fb_ints = rows * W * 2;  // (value, tag) entries
+      const uint64_t per_panel = fb_ints + rows * RR * 2;
+      int* pool = a.pface + td.face_off;
+      int* base = pool + (uint64_t)p * per_panel;
+      PanelIO io;
+      io.top = pj ? pool + (uint64_t)(p - PK) * per_panel : (pk ? a.bnd_tagged[1] : a.bnd_tagged[0]);
+      io.top_stride = W;
+      io.left = pk ? pool + (uint64_t)(p - 1) * per_panel + fb_ints : a.bnd_tagged[2];
+      io.bot = pj + 1 < PJ ? base : nullptr;
+      io.bot_stride = W;
+      io.right = pk + 1 < PK ? base + fb_ints : nullptr;
+      io.gen = gen;
+      io.err = a.ctl + 1;
+      int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
+      sweep_panel<RJ, RK, true>(L, shb, a.sc, a.words, td, pj, pk, io, so);
+      if (so && threadIdx.x == 0 &&
+          __hip_atomic_load(io.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+        __hip_atomic_store(so, INT32_MIN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    (void)RR;
-  }
-}
-
-template <int RJ, int RK>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RJ * RK <= 16 ? 4 : 2))) k_wide(WideArgs a) {
-  constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
-  __shared__ Lds<RJ, RK> L;
-  extern __shared__ uint8_t shb[];
-  const TripletDesc td = a.desc;
-  stage_shifts(shb, a.words, td);
-  const int n0 = (int)td.len[0], n1 = (int)td.len[1], n2 = (int)td.len[2];
-  const int PJ = n1 / H + 1, PK = n2 / W + 1;
-  const uint64_t rows = face_rows((uint32_t)n0);
-  const uint64_t fb_ints = rows * W;
-  const uint64_t per_panel = fb_ints + rows * RR;
-  for (uint32_t q = 0; q < a.panels_per_wave; ++q) {
-    const uint32_t p = a.order[(uint64_t)blockIdx.x * a.panels_per_wave + q];
-    if (p >= a.n_panels) break;
-    const int pj = (int)(p / a.pk_count), pk = (int)(p % a.pk_count);
-    int* base = a.face + (uint64_t)p * per_panel;
-    PanelIO io;
-    io.top = pj ? a.face + (uint64_t)(p - a.pk_count) * per_panel : (pk ? a.bnd_top : a.bnd_top_seed);
-    io.top_stride = W;
-    io.left = pk ? a.face + (uint64_t)(p - 1) * per_panel + fb_ints : a.bnd_left;
-    io.bot = pj + 1 < PJ ? base : nullptr;
-    io.bot_stride = W;
-    io.right = pk + 1 < PK ? base + fb_ints : nullptr;
-    io.top_prog = pj ? a.progress + (p - a.pk_count) : nullptr;
-    io.left_prog = pk ? a.progress + (p - 1) : nullptr;
-    io.my_prog = a.progress + p;
-    io.err = a.progress + a.n_panels;
-    int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
-    sweep_panel<RJ, RK, true>(L, shb, a.sc, a.words, td, pj, pk, io, so);
-    if (so && threadIdx.x == 0 &&
-        __hip_atomic_load(io.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-      *so = INT32_MIN;
   }
 }
 
 // Sentinel faces for panels on the tensor edge: every entry kSent, except
 // the seeded top face, whose entry for k = 0 at slice 0 is 0 (it makes
 // M'(0,0,0) = 0 through the move from the virtual row above).
-__global__ void k_init_boundary(int* top_seed, int* top, int* left, int top_ints, int left_ints,
-                                int seed_index) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < top_ints; i += gridDim.x * blockDim.x) {
-    top_seed[i] = i == seed_index ? 0 : kSent;
-    top[i] = kSent;
+// Sentinel faces for panels on the tensor edge, in the plain layout (one
+// int per entry) and the tagged layout (value, kTagAlways). Every value is
+// kSent except the seeded top faces' entry for k = 0 at slice 0, which is 0
+// (it makes M'(0,0,0) = 0 through the move from the virtual row above).
+__global__ void k_init_boundary(Boundary b, int top_entries, int left_entries, int seed_index) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < top_entries; i += stride) {
+    const int v = i == seed_index ? 0 : kSent;
+    b.plain[0][i] = v;
+    b.plain[1][i] = kSent;
+    b.tagged[0][2 * i] = v;
+    b.tagged[0][2 * i + 1] = kTagAlways;
+    b.tagged[1][2 * i] = kSent;
+    b.tagged[1][2 * i + 1] = kTagAlways;
   }
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < left_ints; i += gridDim.x * blockDim.x)
-    left[i] = kSent;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < left_entries; i += stride) {
+    b.plain[2][i] = kSent;
+    b.tagged[2][2 * i] = kSent;
+    b.tagged[2][2 * i + 1] = kTagAlways;
+  }
 }
 
-__global__ void k_reset(int* p, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+// Before each run: next generation, error flag cleared, queue head zeroed.
+__global__ void k_prepare(int* ctl, int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl[0] = ctl[0] + 1;
+    ctl[1] = 0;
+    counter[0] = 0;
+  }
 }
 
-#define TRIOSEQ_SHAPES(X) X(4, 4) X(8, 4) X(4, 8)
+#define TRIOSEQ_SHAPES(X) X(4, 4, 4) X(4, 4, 2) X(8, 4, 2) X(4, 8, 2)
+#define TRIOSEQ_MODES(X, r, c, w) X(r, c, w, 1) X(r, c, w, 2) X(r, c, w, 3)
 
 }  // namespace
 
 bool shape_supported(const KernelShape& ks) {
-#define X(a, b) if (ks.rj == a && ks.rk == b) return true;
+#define X(a, b, w) if (ks.rj == a && ks.rk == b && ks.wpe == w) return true;
   TRIOSEQ_SHAPES(X)
 #undef X
   return false;
@@ -531,61 +610,41 @@ bool shape_supported(const KernelShape& ks) {
 
 hipError_t launch_init_boundary(const KernelShape& ks, const Boundary& b, hipStream_t s) {
   const int W = panel_cols(ks), RR = right_face_row(ks);
-  const int top_ints = (int)b.rows * W, left_ints = (int)b.rows * RR;
-  hipLaunchKernelGGL(k_init_boundary, dim3(256), dim3(256), 0, s, b.top_seed, b.top, b.left,
-                     top_ints, left_ints, kFacePre * W);
+  const int top_entries = (int)b.rows * W, left_entries = (int)b.rows * RR;
+  hipLaunchKernelGGL(k_init_boundary, dim3(256), dim3(256), 0, s, b, top_entries, left_entries,
+                     kFacePre * W);
   return hipGetLastError();
 }
 
-hipError_t launch_reset(int* p, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int grid = (n + 255) / 256;
-  if (grid > 1024) grid = 1024;
-  hipLaunchKernelGGL(k_reset, dim3(grid), dim3(256), 0, s, p, n);
+hipError_t launch_prepare(int* ctl, int* counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(64), 0, s, ctl, counter);
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const KernelShape& ks, const BatchArgs& a, int grid, hipStream_t s) {
+hipError_t launch_sweep(const KernelShape& ks, int modes, const SweepArgs& a, int grid,
+                        hipStream_t s) {
   const size_t lds = shift_lds_bytes(a.lds_n0);
-#define X(r, c)                                                                \
-  if (ks.rj == r && ks.rk == c) {                                              \
-    hipLaunchKernelGGL((k_batch<r, c>), dim3(grid), dim3(64), lds, s, a);      \
-    return hipGetLastError();                                                  \
+#define Y(r, c, w, m)                                                                  \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m) {                         \
+    hipLaunchKernelGGL((k_sweep<r, c, w, m>), dim3(grid), dim3(64), lds, s, a);        \
+    return hipGetLastError();                                                          \
   }
+#define X(r, c, w) TRIOSEQ_MODES(Y, r, c, w)
   TRIOSEQ_SHAPES(X)
 #undef X
+#undef Y
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_wide(const KernelShape& ks, const WideArgs& a, int grid, hipStream_t s) {
-  const size_t lds = shift_lds_bytes(a.desc.len[0]);
-#define X(r, c)                                                                \
-  if (ks.rj == r && ks.rk == c) {                                              \
-    hipLaunchKernelGGL((k_wide<r, c>), dim3(grid), dim3(64), lds, s, a);       \
-    return hipGetLastError();                                                  \
-  }
-  TRIOSEQ_SHAPES(X)
-#undef X
-  return hipErrorInvalidValue;
-}
-
-hipError_t batch_occupancy(const KernelShape& ks, uint32_t lds_n0, int* waves_per_cu) {
-#define X(r, c)                                                                               \
-  if (ks.rj == r && ks.rk == c)                                                               \
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_batch<r, c>, 64,       \
+hipError_t sweep_occupancy(const KernelShape& ks, int modes, uint32_t lds_n0, int* waves_per_cu) {
+#define Y(r, c, w, m)                                                                         \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m)                                  \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_sweep<r, c, w, m>, 64, \
                                                         shift_lds_bytes(lds_n0));
+#define X(r, c, w) TRIOSEQ_MODES(Y, r, c, w)
   TRIOSEQ_SHAPES(X)
 #undef X
-  return hipErrorInvalidValue;
-}
-
-hipError_t wide_occupancy(const KernelShape& ks, uint32_t lds_n0, int* waves_per_cu) {
-#define X(r, c)                                                                               \
-  if (ks.rj == r && ks.rk == c)                                                               \
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_wide<r, c>, 64,        \
-                                                        shift_lds_bytes(lds_n0));
-  TRIOSEQ_SHAPES(X)
-#undef X
+#undef Y
   return hipErrorInvalidValue;
 }
 

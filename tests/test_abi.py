@@ -107,8 +107,8 @@ def test_bad_plan_options_rejected():
     L = ts.lib()
     lens = np.array([3, 3, 3], dtype=np.uint32)
     h = ctypes.c_void_p()
-    for opts in [ts.PlanOptions(5, 0, 0, 0, 0), ts.PlanOptions(-1, 3, 3, 0, 0),
-                 ts.PlanOptions(-1, 0, 0, -4, 0)]:
+    for opts in [ts.PlanOptions(5, 0, 0, 0, 0, 0), ts.PlanOptions(-1, 3, 3, 0, 0, 0),
+                 ts.PlanOptions(-1, 0, 0, -4, 0, 0), ts.PlanOptions(-1, 4, 4, 0, 0, 3)]:
         assert L.trioseq_plan_create(lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), None, 1,
                                      ctypes.byref(ts.scoring()), ctypes.byref(opts),
                                      ctypes.byref(h)) == -1

@@ -90,12 +90,13 @@ def test_wide_multi_panel(torch_cuda, tile):
         want = oracle.score(t)
         say(f"wide tile={tile} lens={n}")
         got, info = run_plan(torch_cuda, [t], engine=1, tile=tile)
-        assert info["engine"] == 1
+        # A triplet that fits one panel is never split.
+        assert info["engine"] == (1 if info["panels"] > 0 else 0)
         assert int(got[0]) == want, (n, int(got[0]), want, info)
 
 
 def test_wide_with_few_wavefronts(torch_cuda):
-    # More panels than wavefronts: each wavefront walks its panels in order.
+    # More panel jobs than wavefronts: waves pop panels in dependency order.
     rng = np.random.default_rng(24)
     t = tuple(synth.uniform_seq(rng, m) for m in (120, 170, 190))
     want = oracle.score(t)

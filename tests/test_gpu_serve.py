@@ -1,0 +1,137 @@
+"""GPU tests of the continuous-batching server through the C ABI.
+
+Every served score must equal the oracle's (and the score of the same triplet
+scored alone); requests that arrive while others run are admitted into new
+rounds that overlap on the device; bad requests fail alone.
+"""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_28400_amd as ts
+from paper_2605_28400_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def mixed_requests(seed, count, lo=8, hi=160):
+    rng = synth.rng_for(seed)
+    out = []
+    for _ in range(count):
+        n = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        out.append(synth.mutated_triplet(rng, n, float(rng.uniform(0.02, 0.15))))
+    return out
+
+
+def test_served_scores_equal_alone_and_oracle(gpu):
+    reqs = mixed_requests(31, 300)
+    # A few large requests that the server splits into panel jobs.
+    rng = synth.rng_for(32)
+    reqs += [synth.mutated_triplet(rng, n, 0.05) for n in (700, 650)]
+    want = oracle.score_batch(reqs)
+    srv = ts.Server(max_len=1024, max_device_bytes=8 << 30)
+    ids = []
+    say(f"submitting {len(reqs)} requests in waves")
+    for k, t in enumerate(reqs):
+        ids.append(srv.submit(t))
+        if k % 50 == 49:
+            time.sleep(0.002)  # arrivals while earlier rounds are on the GPU
+    got = {}
+    for rid in ids:
+        r = srv.wait(rid, timeout_s=60)
+        assert r["status"] == 0, r
+        got[rid] = r["score"]
+    st = srv.stats()
+    srv.close()
+    scores = np.array([got[i] for i in ids])
+    bad = np.flatnonzero(scores != want)
+    assert bad.size == 0, [(int(q), int(scores[q]), int(want[q])) for q in bad[:5]]
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["rounds"] >= 2
+    assert st["p50_ns"] > 0 and st["p99_ns"] >= st["p50_ns"]
+    # Alone (plain per-triplet path) equals in the mix.
+    for q in (0, 7, 150, len(reqs) - 1):
+        assert ts.score(reqs[q]) == scores[q]
+
+
+def test_concurrent_submitters_and_poll(gpu):
+    reqs = mixed_requests(33, 240, lo=4, hi=120)
+    want = oracle.score_batch(reqs)
+    srv = ts.Server(max_len=256, max_batch=64, max_device_bytes=4 << 30)
+    ids = [None] * len(reqs)
+
+    def submit_range(k0):
+        for q in range(k0, len(reqs), 4):
+            ids[q] = srv.submit(reqs[q])
+            time.sleep(0.0002)
+
+    th = [threading.Thread(target=submit_range, args=(k,)) for k in range(4)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    results = {}
+    t0 = time.time()
+    while len(results) < len(reqs) and time.time() - t0 < 60:
+        for r in srv.poll():
+            results[r["id"]] = r
+        time.sleep(0.001)
+    srv.close()
+    assert len(results) == len(reqs)
+    for q, rid in enumerate(ids):
+        assert results[rid]["status"] == 0 and results[rid]["score"] == want[q]
+
+
+def test_bad_request_fails_alone_and_queue_limits(gpu):
+    srv = ts.Server(max_len=64, max_queue=4, max_device_bytes=1 << 30)
+    good = srv.submit(("ACGT", "ACG", "AGT"))
+    with pytest.raises(ts.TrioseqError) as e:
+        srv.submit(("ACGT", "ACXG", "A"))
+    assert e.value.status == -2
+    with pytest.raises(ts.TrioseqError) as e:
+        srv.submit(("A" * 65, "A", "A"))
+    assert e.value.status == -3
+    assert srv.wait(good, timeout_s=30)["score"] == oracle.score(
+        [synth.from_ascii(b"ACGT"), synth.from_ascii(b"ACG"), synth.from_ascii(b"AGT")])
+    with pytest.raises(ts.TrioseqError) as e:
+        srv.wait(good, timeout_s=1)  # already consumed
+    assert e.value.status == -1
+    # Fill the queue faster than it drains: BUSY appears, nothing is lost.
+    ids, busy = [], 0
+    for _ in range(400):
+        try:
+            ids.append(srv.submit(("ACGTACGT" * 8, "ACGT" * 16, "GT" * 32)))
+        except ts.TrioseqError as err:
+            assert err.status == -7
+            busy += 1
+    for rid in ids:
+        assert srv.wait(rid, timeout_s=30)["status"] == 0
+    srv.close()
+    assert busy + len(ids) == 400
+
+
+def test_destroy_with_work_in_flight(gpu):
+    reqs = mixed_requests(34, 200, lo=50, hi=300)
+    srv = ts.Server(max_len=512, max_device_bytes=4 << 30)
+    for t in reqs:
+        srv.submit(t)
+    srv.close()  # drains queued and in-flight rounds, then frees everything
+    with pytest.raises(Exception):
+        srv.submit(reqs[0])
