@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=4000, help="served: stream length")
     ap.add_argument("--load", type=float, default=0.8,
                     help="served: offered load as a fraction of measured batched throughput")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -157,8 +159,24 @@ def served(args):
     print(json.dumps(rec), flush=True)
 
 
+def copy_calibration(mib: int) -> None:
+    """A plain device-to-device copy of known size: reads and writes mib MiB per launch,
+    so a byte counter's reading for it gives the counter's scale factor."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n, "launches": 5}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.workload == "served":
         if args.gpus != 1:
             print("bench.py runs on one GPU only.", file=sys.stderr)
@@ -216,15 +234,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload.name, "triplets": len(trips), "cells": int(cells),
                    "seed": workload.seed, "scoring": "match +1, mismatch -1, gap -2",
-                   "engine": ["batch", "wide"][info["engine"]],
+                   "engine": ["whole-triplet", "split", "mixed"][info["engine"]],
                    "tile": f"{info['tile_rows']}x{info['tile_cols']}", "grid": info["grid"],
                    "hip_graph": bool(args.graph), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOP/s",
                      "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
                      "kernel_ms": round(ms_events, 4), "ops_per_cell": OPS_PER_CELL,
-                     "kernel": "k_wide (one triplet over many wavefronts)" if info["engine"] == 1
-                     else "k_batch (persistent, one triplet per wavefront)"},
+                     "kernel": "k_sweep (persistent job queue: " +
+                     ["whole-triplet jobs", "panel jobs of a split triplet",
+                      "whole-triplet and panel jobs"][info["engine"]] + ")"},
     }
     if not args.no_cpu_baseline:
         cb, oracle_score = cpu_baseline(workload)

@@ -126,6 +126,28 @@ trioseq_status trioseq_plan_run(trioseq_plan* plan, const uint32_t* d_words, int
 trioseq_status trioseq_plan_get_info(const trioseq_plan* plan, trioseq_plan_info* info);
 trioseq_status trioseq_plan_destroy(trioseq_plan* plan);
 
+/* ---- Autotuning. ------------------------------------------------------ */
+
+typedef struct trioseq_tune_result {
+  trioseq_plan_options best; /* options of the fastest accepted configuration */
+  double best_ms;            /* its mean time per run */
+  double reference_ms;       /* the reference configuration's (default options) */
+  int32_t tried;             /* configurations timed */
+  int32_t rejected;          /* configurations whose scores differed from the reference's */
+} trioseq_tune_result;
+
+/* Times every supported lane-tile / register-budget configuration on the
+ * caller's batch (lens, word_off and d_words as for plans; reps timed runs
+ * each, on hip_stream) and returns the fastest one whose scores equal the
+ * reference configuration's, score for score (a candidate that differs is
+ * rejected and never chosen). The choice is remembered for the process,
+ * keyed by the batch's length profile (triplet count, largest length and
+ * total cells, each bucketed by powers of two): later plan_create calls that
+ * leave tile_rows, tile_cols and waves_per_simd at 0 use it. Synchronous. */
+trioseq_status trioseq_autotune(const uint32_t* lens, const uint64_t* word_off, size_t n,
+                                const trioseq_scoring* sc, const uint32_t* d_words, int32_t reps,
+                                void* hip_stream, trioseq_tune_result* out);
+
 /* ---- Serving: continuous batching of a request stream. ---------------- */
 
 typedef struct trioseq_server trioseq_server;

@@ -48,6 +48,12 @@ class PlanInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_uint64), ("cells", ctypes.c_double)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", PlanOptions), ("best_ms", ctypes.c_double),
+                ("reference_ms", ctypes.c_double), ("tried", ctypes.c_int32),
+                ("rejected", ctypes.c_int32)]
+
+
 class ServeConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_device_bytes", ctypes.c_uint64),
                 ("max_len", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
@@ -70,7 +76,7 @@ class ServeStats(ctypes.Structure):
 EXPORTS = [
     "trioseq_scoring_simple", "trioseq_pack", "trioseq_packed_layout", "trioseq_score",
     "trioseq_score_batch", "trioseq_plan_create", "trioseq_plan_run", "trioseq_plan_get_info",
-    "trioseq_plan_destroy", "trioseq_serve_create", "trioseq_serve_submit", "trioseq_serve_poll",
+    "trioseq_plan_destroy", "trioseq_autotune", "trioseq_serve_create", "trioseq_serve_submit", "trioseq_serve_poll",
     "trioseq_serve_wait", "trioseq_serve_get_stats", "trioseq_serve_destroy",
     "trioseq_last_error", "trioseq_version",
 ]
@@ -109,6 +115,10 @@ def lib() -> ctypes.CDLL:
     L.trioseq_plan_get_info.restype = st
     L.trioseq_plan_destroy.argtypes = [ctypes.c_void_p]
     L.trioseq_plan_destroy.restype = st
+    L.trioseq_autotune.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint64), ctypes.c_size_t,
+                                   P(Scoring), ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                   P(TuneResult)]
+    L.trioseq_autotune.restype = st
     L.trioseq_serve_create.argtypes = [P(ServeConfig), P(Scoring), P(ctypes.c_void_p)]
     L.trioseq_serve_create.restype = st
     L.trioseq_serve_submit.argtypes = [ctypes.c_void_p, P(Triplet), P(ctypes.c_uint64)]
@@ -275,6 +285,26 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def autotune(lens, word_off, d_words, sc: Scoring | None = None, reps: int = 3,
+             stream=None) -> dict:
+    """Times every kernel configuration on this batch and remembers the fastest
+    one whose scores equal the reference configuration's (see trioseq_autotune)."""
+    lens = np.ascontiguousarray(lens, dtype=np.uint32)
+    off = np.ascontiguousarray(word_off, dtype=np.uint64)
+    wp = d_words.data_ptr() if hasattr(d_words, "data_ptr") else int(d_words)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    r = TuneResult()
+    check(lib().trioseq_autotune(lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                 off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                 lens.size // 3, ctypes.byref(sc or _default_scoring()),
+                                 ctypes.c_void_p(wp), reps, _stream_ptr(stream), ctypes.byref(r)))
+    best = {f: getattr(r.best, f) for f, _ in PlanOptions._fields_}
+    return {"best": best, "best_ms": r.best_ms, "reference_ms": r.reference_ms,
+            "tried": r.tried, "rejected": r.rejected}
 
 
 def version() -> str:

@@ -392,6 +392,52 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   return TRIOSEQ_OK;
 }
 
+// Autotuning cache: the best options per batch length profile.
+static std::mutex g_tune_mu;
+static std::vector<std::pair<std::string, trioseq_plan_options>> g_tuned;
+
+static int log2_bucket(double v) {
+  int b = 0;
+  while (v >= 2.0 && b < 80) {
+    v /= 2.0;
+    ++b;
+  }
+  return b;
+}
+
+std::string length_profile(const uint32_t* lens, size_t n) {
+  uint32_t mx = 0;
+  double cells = 0;
+  for (size_t t = 0; t < n; ++t) {
+    const uint32_t* l = lens + 3 * t;
+    mx = std::max({mx, l[0], l[1], l[2]});
+    cells += (double)l[0] * l[1] * l[2];
+  }
+  return std::to_string(log2_bucket((double)n)) + "/" + std::to_string(log2_bucket(mx)) + "/" +
+         std::to_string(log2_bucket(cells));
+}
+
+void apply_tuned(const uint32_t* lens, size_t n, trioseq_plan_options* o) {
+  const std::string key = length_profile(lens, n);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : g_tuned)
+    if (kv.first == key) {
+      o->tile_rows = kv.second.tile_rows;
+      o->tile_cols = kv.second.tile_cols;
+      o->waves_per_simd = kv.second.waves_per_simd;
+    }
+}
+
+static void remember_tuned(const std::string& key, const trioseq_plan_options& o) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& kv : g_tuned)
+    if (kv.first == key) {
+      kv.second = o;
+      return;
+    }
+  g_tuned.emplace_back(key, o);
+}
+
 trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested, int* grid,
                            int* waves_per_cu) {
   int w = 0;
@@ -414,6 +460,7 @@ trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_of
   if (!scp) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: scoring is NULL");
   trioseq_plan_options o{-1, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
+  if (!o.tile_rows && !o.tile_cols && !o.waves_per_simd && lens) apply_tuned(lens, n, &o);
   Layout L;
   trioseq_status st = build_layout(lens, word_off, n, *scp, o, &L);
   if (st != TRIOSEQ_OK) return st;
@@ -607,6 +654,91 @@ static trioseq_status run_host_batch(const trioseq_triplet* t, size_t n, const t
   trioseq_plan_destroy(plan);
   if (st != TRIOSEQ_OK) return st;
   if (e != hipSuccess) return fail_hip(e, "batch");
+  return TRIOSEQ_OK;
+}
+
+trioseq_status trioseq_autotune(const uint32_t* lens, const uint64_t* word_off, size_t n,
+                                const trioseq_scoring* sc, const uint32_t* d_words, int32_t reps,
+                                void* hip_stream, trioseq_tune_result* out) {
+  if (!out || !sc || (n && (!lens || !d_words)))
+    return fail(TRIOSEQ_ERR_INVALID_ARG, "autotune: NULL pointer");
+  if (n == 0) return fail(TRIOSEQ_ERR_INVALID_ARG, "autotune: empty batch");
+  if (reps < 1) reps = 1;
+  hipStream_t s = (hipStream_t)hip_stream;
+  // Candidates: the reference (library defaults) first, then every shape.
+  std::vector<trioseq_plan_options> cands;
+  cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 0});
+  const int shapes[][3] = {{4, 4, 4}, {4, 4, 2}, {8, 4, 2}, {4, 8, 2}};
+  for (const auto& sh : shapes) cands.push_back(trioseq_plan_options{-1, sh[0], sh[1], 0, 0, sh[2]});
+  int32_t* d_ref = nullptr;
+  int32_t* d_out = nullptr;
+  TRIOSEQ_HIP(hipMalloc((void**)&d_ref, n * 4), "hipMalloc");
+  hipError_t e = hipMalloc((void**)&d_out, n * 4);
+  if (e != hipSuccess) {
+    (void)hipFree(d_ref);
+    return fail_hip(e, "hipMalloc");
+  }
+  std::vector<int32_t> ref(n), got(n);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  (void)hipEventCreate(&ev0);
+  (void)hipEventCreate(&ev1);
+  trioseq_tune_result r{};
+  r.best_ms = 1e300;
+  trioseq_status st = TRIOSEQ_OK;
+  for (size_t c = 0; c < cands.size() && st == TRIOSEQ_OK; ++c) {
+    trioseq_plan_options o = cands[c];
+    trioseq_plan* plan = nullptr;
+    // Shapes that need more registers than a budget allows are skipped.
+    if (trioseq_plan_create(lens, word_off, n, sc, &o, &plan) != TRIOSEQ_OK) continue;
+    trioseq_plan_info info;
+    trioseq_plan_get_info(plan, &info);
+    int32_t* dst = c == 0 ? d_ref : d_out;
+    st = trioseq_plan_run(plan, d_words, dst, s);  // warm-up, and the scores to compare
+    if (st == TRIOSEQ_OK && (e = hipStreamSynchronize(s)) != hipSuccess) st = fail_hip(e, "autotune");
+    float ms = 0;
+    if (st == TRIOSEQ_OK) {
+      (void)hipEventRecord(ev0, s);
+      for (int k = 0; k < reps && st == TRIOSEQ_OK; ++k) st = trioseq_plan_run(plan, d_words, d_out, s);
+      (void)hipEventRecord(ev1, s);
+      if (st == TRIOSEQ_OK && (e = hipEventSynchronize(ev1)) != hipSuccess) st = fail_hip(e, "autotune");
+      (void)hipEventElapsedTime(&ms, ev0, ev1);
+      ms /= (float)reps;
+    }
+    trioseq_plan_destroy(plan);
+    if (st != TRIOSEQ_OK) break;
+    ++r.tried;
+    if (c == 0) {
+      if ((e = hipMemcpy(ref.data(), d_ref, n * 4, hipMemcpyDeviceToHost)) != hipSuccess) {
+        st = fail_hip(e, "autotune");
+        break;
+      }
+      r.reference_ms = ms;
+    } else {
+      if ((e = hipMemcpy(got.data(), d_out, n * 4, hipMemcpyDeviceToHost)) != hipSuccess) {
+        st = fail_hip(e, "autotune");
+        break;
+      }
+      if (got != ref) {  // parity gate: never pick a configuration that disagrees
+        ++r.rejected;
+        continue;
+      }
+    }
+    if (ms < r.best_ms) {
+      r.best_ms = ms;
+      r.best = cands[c];
+      r.best.tile_rows = info.tile_rows;
+      r.best.tile_cols = info.tile_cols;
+      r.best.waves_per_simd = c == 0 ? 0 : cands[c].waves_per_simd;
+    }
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  (void)hipFree(d_ref);
+  (void)hipFree(d_out);
+  if (st != TRIOSEQ_OK) return st;
+  if (r.tried == 0) return fail(TRIOSEQ_ERR_DEVICE, "autotune: no configuration could be planned");
+  if (r.best.waves_per_simd) remember_tuned(length_profile(lens, n), r.best);
+  *out = r;
   return TRIOSEQ_OK;
 }
 

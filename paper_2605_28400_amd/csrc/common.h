@@ -73,6 +73,10 @@ struct Layout {
 // Touches no device state.
 trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
                             const trioseq_scoring& sc, const trioseq_plan_options& o, Layout* L);
+// Autotuning cache keyed by a batch's length profile.
+std::string length_profile(const uint32_t* lens, size_t n);
+void apply_tuned(const uint32_t* lens, size_t n, trioseq_plan_options* o);
+
 // Waves to launch for a layout on this device.
 trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested, int* grid,
                            int* waves_per_cu);

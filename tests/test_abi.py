@@ -100,6 +100,7 @@ def test_null_pointers_rejected():
     assert out.value == 123  # untouched on error
     assert L.trioseq_plan_create(None, None, 1, ctypes.byref(ts.scoring()), None, None) == -1
     assert L.trioseq_plan_run(None, None, None, None) == -1
+    assert L.trioseq_autotune(None, None, 1, ctypes.byref(ts.scoring()), None, 1, None, None) == -1
     assert b"NULL" in L.trioseq_last_error() or L.trioseq_last_error()
 
 

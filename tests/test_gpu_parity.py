@@ -206,3 +206,25 @@ def test_alone_equals_in_batch_and_order_free(torch_cuda):
     for q in range(0, 24, 5):
         assert ts.score(trips[q]) == batch[q]
     assert (batch == oracle_scores(trips)).all()
+
+
+def test_autotune_picks_a_parity_clean_config(torch_cuda):
+    torch = torch_cuda
+    trips = synth.fuzz(seed=28, count=300, max_len=120)
+    want = oracle_scores(trips)
+    lens, off, words = ts.pack_batch(trips)
+    d_words = torch.from_numpy(words.view(np.int32)).cuda()
+    say("autotune fuzz batch")
+    r = ts.autotune(lens, off, d_words, reps=2)
+    assert r["tried"] >= 2 and r["rejected"] == 0, r
+    assert r["best_ms"] <= r["reference_ms"] + 1e-9
+    # A plan made afterwards with default options uses the tuned shape.
+    plan = ts.Plan(lens, off, engine=0)
+    info = plan.info()
+    if r["best"]["waves_per_simd"]:
+        assert (info["tile_rows"], info["tile_cols"]) == (r["best"]["tile_rows"], r["best"]["tile_cols"])
+    d_scores = torch.full((len(trips),), -7, dtype=torch.int32, device="cuda")
+    plan.run(d_words, d_scores)
+    torch.cuda.synchronize()
+    plan.close()
+    assert (d_scores.cpu().numpy() == want).all()
