@@ -49,8 +49,14 @@ struct Request {
 
 struct Slot {
   hipStream_t stream = nullptr;
-  char* arena = nullptr;  // device
+  char* arena = nullptr;  // device: packed words, job tables, whole-triplet workspace
   uint64_t arena_bytes = 0;
+  // Device region that only ever holds tagged panel faces ((value, tag)
+  // pairs at 8-byte alignment), zeroed once. Because no plain data is ever
+  // written here, every stale tag slot holds an older run generation of this
+  // slot (or 0), never a value that could pass for the current one.
+  int* tagged = nullptr;
+  uint64_t tagged_bytes = 0;
   int* ctl = nullptr;     // device: [0] generation, [1] error flag, [64] queue head
   uint32_t* h_words = nullptr;  // pinned staging
   uint64_t h_words_cap = 0;
@@ -105,11 +111,11 @@ namespace {
 
 uint64_t align256(uint64_t v) { return (v + 255) / 256 * 256; }
 
-// Device bytes a round needs in a slot arena.
-uint64_t round_bytes(const Layout& L, uint64_t words, int grid) {
+// Device bytes a round needs in a slot arena (the panel-face pool lives in
+// the slot's tagged region instead: L.pool_ints * 4 bytes).
+uint64_t arena_need(const Layout& L, uint64_t words, int grid) {
   return align256(words * 4) + align256(L.desc.size() * sizeof(TripletDesc)) +
-         align256(L.jobs.size() * sizeof(JobDesc)) +
-         align256((uint64_t)grid * L.face_stride * 4) + align256(L.pool_ints * 4);
+         align256(L.jobs.size() * sizeof(JobDesc)) + align256((uint64_t)grid * L.face_stride * 4);
 }
 
 void record_result(trioseq_server* s, const Request& r, int32_t score, int32_t status, uint64_t t) {
@@ -157,8 +163,8 @@ trioseq_status launch_round(trioseq_server* s, Slot& sl, std::vector<Request>& b
     *err = trioseq_last_error();
     return st;
   }
-  if (round_bytes(L, words, grid) > sl.arena_bytes || words > sl.h_words_cap ||
-      L.jobs.size() > sl.h_meta_cap || n > sl.max_batch) {
+  if (arena_need(L, words, grid) > sl.arena_bytes || L.pool_ints * 4 > sl.tagged_bytes ||
+      words > sl.h_words_cap || L.jobs.size() > sl.h_meta_cap || n > sl.max_batch) {
     *err = "round does not fit its slot";
     return TRIOSEQ_ERR_TOO_LARGE;
   }
@@ -180,8 +186,7 @@ trioseq_status launch_round(trioseq_server* s, Slot& sl, std::vector<Request>& b
   JobDesc* d_jobs = (JobDesc*)a;
   a += align256(L.jobs.size() * sizeof(JobDesc));
   int* d_face = (int*)a;
-  a += align256((uint64_t)grid * L.face_stride * 4);
-  int* d_pface = (int*)a;
+  int* d_pface = sl.tagged;
 
   hipError_t e = hipSuccess;
   if (words) e = hipMemcpyAsync(d_words, sl.h_words, words * 4, hipMemcpyHostToDevice, sl.stream);
@@ -301,6 +306,7 @@ void free_server(trioseq_server* s) {
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
     (void)hipFree(sl.arena);
+    (void)hipFree(sl.tagged);
     (void)hipFree(sl.ctl);
     (void)hipHostFree(sl.h_words);
     (void)hipHostFree(sl.h_desc);
@@ -341,7 +347,10 @@ trioseq_status trioseq_serve_create(const trioseq_serve_config* cfg, const trios
   }
   uint64_t budget = cfg->max_device_bytes ? cfg->max_device_bytes : s->dp.hbm_bytes / 4;
   const uint64_t per_slot = budget / kSlots / 256 * 256;
-  // The largest single request must fit a slot on its own.
+  // The largest single request must fit a slot on its own. A slot's tagged
+  // region is sized for that request's panel faces; the rest of the slot
+  // budget is its arena.
+  uint64_t tagged_bytes = 0;
   {
     const uint32_t m = cfg->max_len;
     const uint32_t lens[3] = {m, m, m};
@@ -354,7 +363,9 @@ trioseq_status trioseq_serve_create(const trioseq_serve_config* cfg, const trios
       delete s;
       return st;
     }
-    if (round_bytes(L, 3ull * ((m + 15) / 16), grid) > per_slot) {
+    tagged_bytes = align256(L.pool_ints * 4);
+    if (tagged_bytes >= per_slot ||
+        arena_need(L, 3ull * ((m + 15) / 16), grid) > per_slot - tagged_bytes) {
       delete s;
       return fail(TRIOSEQ_ERR_TOO_LARGE, "serve_create: max_device_bytes too small for max_len");
     }
@@ -373,14 +384,19 @@ trioseq_status trioseq_serve_create(const trioseq_serve_config* cfg, const trios
   const uint64_t max_jobs = (uint64_t)s->cfg.max_batch + 65536;
   for (Slot& sl : s->slots) {
     sl.max_batch = s->cfg.max_batch;
-    sl.arena_bytes = per_slot;
+    sl.arena_bytes = per_slot - tagged_bytes;
+    sl.tagged_bytes = tagged_bytes;
     if ((e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking)) != hipSuccess)
       return bail(e, "hipStreamCreate");
     if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess)
       return bail(e, "hipEventCreate");
-    if ((e = hipMalloc((void**)&sl.arena, per_slot)) != hipSuccess) return bail(e, "hipMalloc arena");
-    // Tagged panel faces in the arena must never match a run: start at 0.
-    if ((e = hipMemset(sl.arena, 0, per_slot)) != hipSuccess) return bail(e, "hipMemset arena");
+    if ((e = hipMalloc((void**)&sl.arena, sl.arena_bytes)) != hipSuccess) return bail(e, "hipMalloc arena");
+    if (tagged_bytes) {
+      if ((e = hipMalloc((void**)&sl.tagged, tagged_bytes)) != hipSuccess)
+        return bail(e, "hipMalloc tagged faces");
+      // Tag 0 belongs to no run (generations start at 1).
+      if ((e = hipMemset(sl.tagged, 0, tagged_bytes)) != hipSuccess) return bail(e, "hipMemset");
+    }
     if ((e = hipMalloc((void**)&sl.ctl, 512)) != hipSuccess) return bail(e, "hipMalloc");
     if ((e = hipMemset(sl.ctl, 0, 512)) != hipSuccess) return bail(e, "hipMemset");
     sl.h_words_cap = max_words;

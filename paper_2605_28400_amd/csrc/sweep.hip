@@ -90,12 +90,14 @@ struct Lds {
   int wsync;
 };
 
+// Face buffers. A bottom face holds W entries per slice row and a right face
+// RR = H + 4 (entry 0: the corner for the next panel; 1..3 unused); rows are
+// padded by kFacePre before slice 0. Every stride is a compile-time
+// constant, so step offsets fold into the instructions' immediate offsets.
 struct PanelIO {
-  const int* top;     // bottom face of the panel above (padded rows), or a sentinel face
-  uint32_t top_stride;
+  const int* top;     // bottom face of the panel above, or a sentinel face
   const int* left;    // right face of the panel to the left, or a sentinel face
   int* bot;           // this panel's bottom face (nullptr: not needed)
-  uint32_t bot_stride;
   int* right;         // this panel's right face (nullptr: not needed)
   int gen;            // run generation: wide-engine faces carry it as a tag
   int* err;           // set when a tag wait gave up (wide engine)
@@ -210,16 +212,13 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   // Face resources. Rows are padded (kFacePre before slice 0), so every
   // staging load and every edge store stays inside its buffer.
   const uint32_t frows = face_rows((uint32_t)n0);
-  const Rsrc r_top = make_rsrc(io.top, (uint64_t)frows * io.top_stride * 4 * ES);
-  const Rsrc r_left = make_rsrc(io.left, (uint64_t)frows * RR * 4 * ES);
-  // An absent output gets an empty resource: its stores are all dropped.
-  const Rsrc r_bot = make_rsrc(io.bot ? io.bot : io.top,
-                               io.bot ? (uint64_t)frows * io.bot_stride * 4 * ES : 0);
-  const Rsrc r_right = make_rsrc(io.right ? io.right : io.left,
-                                 io.right ? (uint64_t)frows * RR * 4 * ES : 0);
   // Row strides in bytes.
-  const uint32_t ts = io.top_stride * 4u * ES, bs = io.bot_stride * 4u * ES;
-  constexpr uint32_t RRB = RR * 4u * ES;
+  constexpr uint32_t ts = W * 4u * ES, bs = ts, RRB = RR * 4u * ES;
+  const Rsrc r_top = make_rsrc(io.top, (uint64_t)frows * ts);
+  const Rsrc r_left = make_rsrc(io.left, (uint64_t)frows * RRB);
+  // An absent output gets an empty resource: its stores are all dropped.
+  const Rsrc r_bot = make_rsrc(io.bot ? io.bot : io.top, io.bot ? (uint64_t)frows * bs : 0);
+  const Rsrc r_right = make_rsrc(io.right ? io.right : io.left, io.right ? (uint64_t)frows * RRB : 0);
 
   // Staging. Value q of a chunk is, for this lane, entry v = lane + 64 q of
   // one of three LDS rings (top face, corners, left face). Within a ring a
@@ -372,7 +371,16 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   const uint32_t vo_corner = (x == kGK - 1 && y == 0) ? (uint32_t)((kFacePre - x) * (int)RRB) : kOob;
   const int sh_base = kFacePre - y - x;
 
+  // Store offsets of this chunk. Stores take their whole offset in the VGPR
+  // (chunk base) plus the immediate (step and entry), never an SGPR offset:
+  // gfx950 can read the data registers of a store wider than 64 bits after
+  // the next instruction has overwritten them when the store has an SGPR
+  // offset, and the compiler only separates the two for stores without one.
+  // Lanes at kOob stay out of range (the chunk base is far below 2^28).
   auto run_chunk = [&](int c, bool cap) {
+    const uint32_t cbase = (uint32_t)(c * kChunk);
+    const uint32_t vb = vo_bot + cbase * bs, vr = vo_right + cbase * RRB,
+                   vc = vo_corner + cbase * RRB;
     const int rr = (c & 1) * kChunk;
     const int* tb = t_base + rr * t_str;
     const int* cb = c_base + rr * c_str;
@@ -427,25 +435,24 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
 #pragma unroll
         for (int cc = 0; cc < RK; cc += 2)
           __builtin_amdgcn_raw_buffer_store_b128((v4i){N[RJ - 1][cc], g, N[RJ - 1][cc + 1], g}, r_bot,
-                                                 vo_bot + cc * 8, (uint32_t)t * bs, COH);
+                                                 vb + (s * bs + cc * 8), 0, COH);
 #pragma unroll
         for (int r = 0; r < RJ; r += 2)
           __builtin_amdgcn_raw_buffer_store_b128((v4i){N[r][RK - 1], g, N[r + 1][RK - 1], g}, r_right,
-                                                 vo_right + r * 8, (uint32_t)t * RRB, COH);
-        __builtin_amdgcn_raw_buffer_store_b64((v2i){T[RK - 1], g}, r_right, vo_corner,
-                                              (uint32_t)t * RRB, COH);
+                                                 vr + (s * RRB + r * 8), 0, COH);
+        __builtin_amdgcn_raw_buffer_store_b64((v2i){T[RK - 1], g}, r_right, vc + s * RRB, 0, COH);
       } else {
 #pragma unroll
         for (int cc = 0; cc < RK; cc += 4)
           __builtin_amdgcn_raw_buffer_store_b128(
               (v4i){N[RJ - 1][cc], N[RJ - 1][cc + 1], N[RJ - 1][cc + 2], N[RJ - 1][cc + 3]}, r_bot,
-              vo_bot + cc * 4, (uint32_t)t * bs, COH);
+              vb + (s * bs + cc * 4), 0, COH);
 #pragma unroll
         for (int r = 0; r < RJ; r += 4)
           __builtin_amdgcn_raw_buffer_store_b128(
               (v4i){N[r][RK - 1], N[r + 1][RK - 1], N[r + 2][RK - 1], N[r + 3][RK - 1]}, r_right,
-              vo_right + r * 4, (uint32_t)t * RRB, COH);
-        __builtin_amdgcn_raw_buffer_store_b32(T[RK - 1], r_right, vo_corner, (uint32_t)t * RRB, COH);
+              vr + (s * RRB + r * 4), 0, COH);
+        __builtin_amdgcn_raw_buffer_store_b32(T[RK - 1], r_right, vc + s * RRB, 0, COH);
       }
 
       if (cap) {
@@ -520,16 +527,16 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
     const int PJ = n1 / H + 1, PK = n2 / W + 1;
     const uint64_t rows = face_rows((uint32_t)n0);
     if ((MODES & 1) && jd.panel == kWholeTriplet) {
+      // Bottom faces, one per panel column ([PK][rows][W]), then the right face.
       int* fb = face;
       int* fr = face + rows * (uint64_t)(PK * W);
       for (int pj = 0; pj < PJ; ++pj) {
         for (int pk = 0; pk < PK; ++pk) {
+          int* col = fb + (uint64_t)pk * rows * W;
           PanelIO io;
-          io.top = pj ? fb + pk * W : (pk ? a.bnd_plain[1] : a.bnd_plain[0]);
-          io.top_stride = pj ? (uint32_t)(PK * W) : (uint32_t)W;
+          io.top = pj ? col : (pk ? a.bnd_plain[1] : a.bnd_plain[0]);
           io.left = pk ? fr : a.bnd_plain[2];
-          io.bot = pj + 1 < PJ ? fb + pk * W : nullptr;
-          io.bot_stride = (uint32_t)(PK * W);
+          io.bot = pj + 1 < PJ ? col : nullptr;
           io.right = pk + 1 < PK ? fr : nullptr;
           io.gen = 0;
           io.err = nullptr;
@@ -546,10 +553,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       int* base = pool + (uint64_t)p * per_panel;
       PanelIO io;
       io.top = pj ? pool + (uint64_t)(p - PK) * per_panel : (pk ? a.bnd_tagged[1] : a.bnd_tagged[0]);
-      io.top_stride = W;
       io.left = pk ? pool + (uint64_t)(p - 1) * per_panel + fb_ints : a.bnd_tagged[2];
       io.bot = pj + 1 < PJ ? base : nullptr;
-      io.bot_stride = W;
       io.right = pk + 1 < PK ? base + fb_ints : nullptr;
       io.gen = gen;
       io.err = a.ctl + 1;
