@@ -30,6 +30,26 @@ OPS_PER_CELL = 7
 
 WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served")
 
+# HBM bytes per launch of the sweep kernel, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs scaled by the same counters on a plain 1 GiB copy (summaries
+# with the commands are under profiles/). Each figure holds only for the kernel
+# source it was measured on; for any other source the field is null.
+TRAFFIC = {
+    "single_1024x1000x1048": (2.0975e9, "0247fbc75818dfc9"),
+    "batch_8192_len100-400": (1.5054e11, "0247fbc75818dfc9"),
+}
+
+
+def measured_traffic(workload_name: str):
+    import hashlib
+    entry = TRAFFIC.get(workload_name)
+    if entry is None:
+        return None
+    src = os.path.join(ROOT, "paper_2605_28400_amd", "csrc", "sweep.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return entry[0] if sha == entry[1] else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -239,7 +259,8 @@ def main():
                    "hip_graph": bool(args.graph), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOP/s",
-                     "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_INT32_TOPS, 4),
+                     "traffic": measured_traffic(workload.name),
                      "kernel_ms": round(ms_events, 4), "ops_per_cell": OPS_PER_CELL,
                      "kernel": "k_sweep (persistent job queue: " +
                      ["whole-triplet jobs", "panel jobs of a split triplet",
