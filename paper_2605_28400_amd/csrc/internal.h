@@ -22,11 +22,14 @@ constexpr int kRing = 2 * kChunk;
 // Longest sequence accepted on the sweep axis: its per-slice lookup shifts
 // live in LDS, one byte per slice.
 constexpr int kMaxSweepLen = 16384;
-// Face buffers carry kFacePre rows before slice 0 and kFacePost after slice
-// n0, so the skewed fill/drain steps store into padding instead of testing.
-constexpr int kFacePre = 16;
-constexpr int kFacePost = 24;
-__host__ __device__ inline uint32_t face_rows(uint32_t n0) { return n0 + 1 + kFacePre + kFacePost; }
+// The per-slice lookup shifts in LDS are padded by kShiftPre entries before
+// slice 0 (skewed lanes read slices down to -kSkew).
+constexpr int kShiftPre = 16;
+// Face buffers hold one row per producer step. A sweep of n0 + 1 slices runs
+// at most n0 + 1 + kSkew + kChunk - 1 steps, and consumers read up to
+// kGJ - 1 rows past the producer's last, so n0 + 1 + kSkew + 2 * kChunk rows
+// cover every access.
+__host__ __device__ inline uint32_t face_rows(uint32_t n0) { return n0 + 1 + kSkew + 2 * kChunk; }
 // Dynamic LDS bytes for the sweep shifts of a sequence of length n0.
 __host__ __device__ inline uint32_t shift_lds_bytes(uint32_t n0) { return (n0 + 64 + 15) & ~15u; }
 

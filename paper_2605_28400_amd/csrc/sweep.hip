@@ -43,8 +43,6 @@
 //    triplet split over many waves, whose faces travel through HBM as
 //    (value, run-tag) pairs with device-coherent accesses (see the
 //    hand-over notes below).
-#include <type_traits>
-
 #include "internal.h"
 
 namespace trioseq {
@@ -90,10 +88,15 @@ struct Lds {
   int wsync;
 };
 
-// Face buffers. A bottom face holds W entries per slice row and a right face
-// RR = H + 4 (entry 0: the corner for the next panel; 1..3 unused); rows are
-// padded by kFacePre before slice 0. Every stride is a compile-time
-// constant, so step offsets fold into the instructions' immediate offsets.
+// Face buffers hold one row per step of the producing wavefront: at step t
+// its edge lanes write row t of its bottom face (W entries, lane (7,x) at
+// slice t - 7 - x) and of its right face (RR = H + 4 entries: entry 0 the
+// corner for the next panel, 1..3 unused, 4 + r the column of lane (r/RJ, 7)
+// at slice t - r/RJ - 7). A consumer lane at step t' needs exactly the
+// producer's row t' + 7 (its halo of slice t' - x or t' - y), so every
+// step writes one contiguous row and every chunk of steps reads contiguous
+// rows. Every stride is a compile-time constant, so step offsets fold into
+// the instructions' immediate offsets.
 struct PanelIO {
   const int* top;     // bottom face of the panel above, or a sentinel face
   const int* left;    // right face of the panel to the left, or a sentinel face
@@ -114,8 +117,18 @@ struct PanelIO {
 // kTagAlways, valid in every run.
 constexpr int kCohNone = 0;
 constexpr int kCohDevice = 16;              // SC1
-constexpr int kVolatile = (int)(1u << 31);  // compiler-side: never merge or hoist the load
 constexpr int kTagAlways = 0x7FFFFFFF;
+
+// A zero the compiler cannot see through. Re-reads of stale face entries add
+// it to their scalar offset, so each retry is a distinct load that is neither
+// merged with nor hoisted above an earlier one, while staying an ordinary
+// (non-volatile) device-coherent load: all re-reads of a chunk are in flight
+// together and share one wait.
+__device__ __forceinline__ uint32_t opaque_zero() {
+  uint32_t z;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+  return z;
+}
 
 // Bound on the wait for a stale chunk, in ticks of the 100 MHz wall clock.
 // Every wave leaves the loop: past the limit it raises the error flag and
@@ -126,14 +139,14 @@ constexpr uint64_t kWaitTicks = 200000000ull;  // 2 s
 typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-// Per-slice lookup shifts: shb[i + kFacePre] = 8 * code(S0[i-1]) for slices
-// 1..n0, 0 elsewhere; covers slices -kFacePre .. n0 + 47.
+// Per-slice lookup shifts: shb[i + kShiftPre] = 8 * code(S0[i-1]) for slices
+// 1..n0, 0 elsewhere; covers slices -kShiftPre .. n0 + 47.
 __device__ __forceinline__ void stage_shifts(uint8_t* shb, const uint32_t* __restrict__ words,
                                              const TripletDesc& td) {
   const int n0 = (int)td.len[0];
   const int total = n0 + 64;
   for (int q = threadIdx.x; q < total; q += 64) {
-    const int i = q - kFacePre;
+    const int i = q - kShiftPre;
     uint32_t v = 0;
     if (i >= 1 && i <= n0) v = residue_at(words, td.off[0], (uint32_t)(i - 1)) << 3;
     shb[q] = (uint8_t)v;
@@ -209,8 +222,7 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   const int rsel = n1 - j0, csel = n2 - k0;
   const bool own = score_out && rsel >= 0 && rsel < RJ && csel >= 0 && csel < RK;
 
-  // Face resources. Rows are padded (kFacePre before slice 0), so every
-  // staging load and every edge store stays inside its buffer.
+  // Face resources: face_rows(n0) rows cover every staging load and store.
   const uint32_t frows = face_rows((uint32_t)n0);
   // Row strides in bytes.
   constexpr uint32_t ts = W * 4u * ES, bs = ts, RRB = RR * 4u * ES;
@@ -221,51 +233,55 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   const Rsrc r_right = make_rsrc(io.right ? io.right : io.left, io.right ? (uint64_t)frows * RRB : 0);
 
   // Staging. Value q of a chunk is, for this lane, entry v = lane + 64 q of
-  // one of three LDS rings (top face, corners, left face). Within a ring a
-  // q step advances by whole rows (ring widths divide 64), so each ring needs
-  // one base voffset per lane plus a scalar increment per q, and the LDS
+  // one of three LDS rings (top face, corners, left face). Ring row s of
+  // chunk c serves step t' = c * kChunk + s: the top and left rings hold
+  // producer row t' + 7, the corner of top-edge lane x >= 1 is entry
+  // x*RK - 1 of top row t' + 6 (what lane x - 1 saw one step earlier) and
+  // that of lane 0 is entry 0 of left row t' + 7. Within a ring a q step
+  // advances by whole rows (ring widths divide 64), so each ring needs one
+  // base voffset per lane plus a scalar increment per q, and the LDS
   // destination is simply ring base + v. Faces always exist: at the tensor
-  // edge they are sentinel buffers, and padding rows hold the fill-phase
-  // values of the producing panel, which stay within 2^24 of kSent.
+  // edge they are sentinel buffers, and rows written during the producer's
+  // fill steps hold values within 2^24 of kSent.
   constexpr int QT = kChunk * W / 64, QC = kChunk * kGK / 64, QL = kChunk * H / 64;
   constexpr int NPF = QT + QC + QL;
   constexpr int RT = 64 / W, RL = 64 / H;  // ring rows per q
   static_assert(64 % W == 0 && 64 % H == 0 && QC == 1, "ring widths must divide 64");
   const int eT = lane % W;
-  const uint32_t offT = (uint32_t)((kFacePre + lane / W - eT / RK) * (int)ts + eT * 4 * ES);
+  const uint32_t offT = (uint32_t)((kGJ - 1 + lane / W) * (int)ts + eT * 4 * ES);
   const int eC = lane % kGK;
   const bool corner_from_left = eC == 0;
   const uint32_t offC = corner_from_left
-                            ? (uint32_t)((kFacePre + lane / kGK) * (int)RRB)
-                            : (uint32_t)((kFacePre + lane / kGK - eC) * (int)ts + (eC * RK - 1) * 4 * ES);
+                            ? (uint32_t)((kGK - 1 + lane / kGK) * (int)RRB)
+                            : (uint32_t)((kGJ - 2 + lane / kGK) * (int)ts + (eC * RK - 1) * 4 * ES);
   const int eL = lane % H;
-  const uint32_t offL = (uint32_t)((kFacePre + lane / H - eL / RJ) * (int)RRB + (4 + eL) * 4 * ES);
+  const uint32_t offL = (uint32_t)((kGK - 1 + lane / H) * (int)RRB + (4 + eL) * 4 * ES);
   // Slice of entry q in chunk c is c * kChunk + rel(q).
   const int relT = lane / W - eT / RK, relC = lane / kGK - eC, relL = lane / H - eL / RJ;
   auto rel_of = [&](int q) {
     return q < QT ? relT + q * RT : q < QT + QC ? relC : relL + (q - QT - QC) * RL;
   };
 
-  // Face entry q of chunk c for this lane: (value, tag); tag is unused in
-  // the batch engine. Re-reads of stale entries are volatile so that they
-  // really go to memory again instead of reusing the first load.
-  auto load_entry = [&](int q, int c, auto retry_tag) -> v2i {
-    constexpr int LDC = decltype(retry_tag)::value ? (COH | kVolatile) : COH;
+  // Face entry q of chunk c for this lane: (value, tag); the tag is unused
+  // for whole-triplet jobs. z is added to the scalar offset (0, or an opaque
+  // zero for re-reads).
+  auto load_entry = [&](int q, int c, uint32_t z) -> v2i {
+    constexpr int LDC = COH;
     const uint32_t base = (uint32_t)(c * kChunk);
     if (q < QT) {
-      const uint32_t so = (base + q * RT) * ts;
+      const uint32_t so = (base + q * RT) * ts + z;
       if (WIDE) return __builtin_amdgcn_raw_buffer_load_b64(r_top, offT, so, LDC);
       return (v2i){(int)__builtin_amdgcn_raw_buffer_load_b32(r_top, offT, so, LDC), 0};
     } else if (q < QT + QC) {
       const uint32_t ot = corner_from_left ? kOob : offC, ol = corner_from_left ? offC : kOob;
       if (WIDE)
-        return __builtin_amdgcn_raw_buffer_load_b64(r_top, ot, base * ts, LDC) |
-               __builtin_amdgcn_raw_buffer_load_b64(r_left, ol, base * RRB, LDC);
-      return (v2i){(int)(__builtin_amdgcn_raw_buffer_load_b32(r_top, ot, base * ts, LDC) |
-                         __builtin_amdgcn_raw_buffer_load_b32(r_left, ol, base * RRB, LDC)),
+        return __builtin_amdgcn_raw_buffer_load_b64(r_top, ot, base * ts + z, LDC) |
+               __builtin_amdgcn_raw_buffer_load_b64(r_left, ol, base * RRB + z, LDC);
+      return (v2i){(int)(__builtin_amdgcn_raw_buffer_load_b32(r_top, ot, base * ts + z, LDC) |
+                         __builtin_amdgcn_raw_buffer_load_b32(r_left, ol, base * RRB + z, LDC)),
                    0};
     } else {
-      const uint32_t so = (base + (q - QT - QC) * RL) * RRB;
+      const uint32_t so = (base + (q - QT - QC) * RL) * RRB + z;
       if (WIDE) return __builtin_amdgcn_raw_buffer_load_b64(r_left, offL, so, LDC);
       return (v2i){(int)__builtin_amdgcn_raw_buffer_load_b32(r_left, offL, so, LDC), 0};
     }
@@ -274,19 +290,20 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   auto stage_load = [&](int c) {
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
-      const v2i e = load_entry(q, c, std::false_type());
+      const v2i e = load_entry(q, c, 0u);
       pf[q] = e.x;
       pt[q] = e.y;
     }
   };
-  // Wide engine: wait until every entry the sweep uses carries this run's
+  // Panel jobs: wait until every entry the sweep uses carries this run's
   // tag. Entries of slices past n0 are never written by the producer (its
   // drain stops earlier) and only feed cells past n0, so they are skipped.
-  // While the chunk is stale only two lanes poll, each one probe entry that
-  // its producer writes last for this chunk (slice min(c*kChunk+7, n0),
-  // entry 0), with a pause between polls; the whole chunk is re-read once
-  // both probes are current. Waiting waves thus put almost no load on the
-  // memory system the producers need.
+  // A stale chunk is first re-read at once (twice: the producer is usually
+  // only a few steps behind). After that only two lanes poll, each one probe
+  // entry that its producer writes last for this chunk (slice
+  // min(c*kChunk+7, n0), entry 0, in row slice + 7), with a pause between polls, and the stale
+  // entries are re-read once both probes are current. Waiting waves thus put
+  // almost no load on the memory system the producers need.
   const bool probe_top = lane == 0 && pj > 0, probe_left = lane == 1 && pk > 0;
   auto stage_validate = [&](int c) {
     if (!WIDE) return;
@@ -299,27 +316,28 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
     if (chunk_ok()) return;
     const uint64_t t_start = wall_clock64();
     const int ps = min(c * kChunk + kChunk - 1, n0);
-    const uint32_t probe_off = probe_top ? (uint32_t)((kFacePre + ps) * (int)ts)
-                                         : (uint32_t)((kFacePre + ps) * (int)RRB + 4 * 4 * ES);
-    for (;;) {
+    const uint32_t probe_off = probe_top ? (uint32_t)((ps + kGJ - 1) * (int)ts)
+                                         : (uint32_t)((ps + kGK - 1) * (int)RRB + 4 * 4 * ES);
+    for (int attempt = 0;; ++attempt) {
       if (wall_clock64() - t_start > kWaitTicks) {
         if (lane == 0) __hip_atomic_store(io.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
-      __builtin_amdgcn_s_sleep(16);
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      bool probe_ok = true;
-      if (probe_top)
-        probe_ok = ((v2i)__builtin_amdgcn_raw_buffer_load_b64(r_top, probe_off, 0u,
-                                                              kCohDevice | kVolatile)).y >= io.gen;
-      if (probe_left)
-        probe_ok = ((v2i)__builtin_amdgcn_raw_buffer_load_b64(r_left, probe_off, 0u,
-                                                              kCohDevice | kVolatile)).y >= io.gen;
-      if (__builtin_amdgcn_ballot_w64(!probe_ok) != 0) continue;
+      if (attempt >= 2) {
+        __builtin_amdgcn_s_sleep(8);
+        const uint32_t z = opaque_zero();
+        bool probe_ok = true;
+        if (probe_top)
+          probe_ok = ((v2i)__builtin_amdgcn_raw_buffer_load_b64(r_top, probe_off, z, kCohDevice)).y >= io.gen;
+        if (probe_left)
+          probe_ok = ((v2i)__builtin_amdgcn_raw_buffer_load_b64(r_left, probe_off, z, kCohDevice)).y >= io.gen;
+        if (__builtin_amdgcn_ballot_w64(!probe_ok) != 0) continue;
+      }
+      const uint32_t z = opaque_zero();
 #pragma unroll
       for (int q = 0; q < NPF; ++q)
         if (pt[q] < io.gen && c * kChunk + rel_of(q) <= n0) {
-          const v2i e = load_entry(q, c, std::true_type());
+          const v2i e = load_entry(q, c, z);
           pf[q] = e.x;
           pt[q] = e.y;
         }
@@ -363,13 +381,11 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   const int l_str = x0 ? H : 0;
 
   // Edge stores: bottom row (y = 7), right column (x = 7), and the corner
-  // for the next panel (lane (0,7)). The row of slice i is i + kFacePre.
-  const uint32_t vo_bot =
-      (y == kGJ - 1) ? (uint32_t)((kFacePre - y - x) * (int)bs + x * RK * 4 * ES) : kOob;
-  const uint32_t vo_right =
-      (x == kGK - 1) ? (uint32_t)((kFacePre - y - x) * (int)RRB + (4 + y * RJ) * 4 * ES) : kOob;
-  const uint32_t vo_corner = (x == kGK - 1 && y == 0) ? (uint32_t)((kFacePre - x) * (int)RRB) : kOob;
-  const int sh_base = kFacePre - y - x;
+  // for the next panel (lane (0,7)), all into row t at step t.
+  const uint32_t vo_bot = (y == kGJ - 1) ? (uint32_t)(x * RK * 4 * ES) : kOob;
+  const uint32_t vo_right = (x == kGK - 1) ? (uint32_t)((4 + y * RJ) * 4 * ES) : kOob;
+  const uint32_t vo_corner = (x == kGK - 1 && y == 0) ? 0u : kOob;
+  const int sh_base = kShiftPre - y - x;
 
   // Store offsets of this chunk. Stores take their whole offset in the VGPR
   // (chunk base) plus the immediate (step and entry), never an SGPR offset:
@@ -616,8 +632,9 @@ bool shape_supported(const KernelShape& ks) {
 hipError_t launch_init_boundary(const KernelShape& ks, const Boundary& b, hipStream_t s) {
   const int W = panel_cols(ks), RR = right_face_row(ks);
   const int top_entries = (int)b.rows * W, left_entries = (int)b.rows * RR;
+  // The top lane x = 0 reads slice 0 from row kGJ - 1 (entry 0).
   hipLaunchKernelGGL(k_init_boundary, dim3(256), dim3(256), 0, s, b, top_entries, left_entries,
-                     kFacePre * W);
+                     (kGJ - 1) * W);
   return hipGetLastError();
 }
 
