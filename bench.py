@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--engine", type=int, default=-1)
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--requests", type=int, default=4000, help="served: stream length")
+    ap.add_argument("--requests", type=int, default=100_000, help="served: stream length")
     ap.add_argument("--load", type=float, default=0.8,
                     help="served: offered load as a fraction of measured batched throughput")
     ap.add_argument("--autotune", type=int, default=1,
@@ -117,65 +117,71 @@ def cpu_baseline(workload, budget_s: float = 20.0):
             "seconds": round(dt, 3)}, None
 
 
-def per_triplet(ts, torch, trips, sample: int, stream, batch_scores):
-    """The plain per-triplet path on the same GPU: the first `sample` triplets,
-    each with its own plan (inputs resident in HBM, plans built untimed),
-    launched back to back on one stream. Scores must equal the batched ones."""
-    sub = trips[:sample]
-    plans, bufs = [], []
-    for t in sub:
-        lens, off, words = ts.pack_batch([t])
-        plans.append(ts.Plan(lens, off))
-        bufs.append((torch.from_numpy(words.view(np.int32)).cuda(),
-                     torch.zeros(1, dtype=torch.int32, device="cuda")))
-    for p, (w, sc) in zip(plans, bufs):
-        p.run(w, sc, stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for p, (w, sc) in zip(plans, bufs):
-        p.run(w, sc, stream)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    alone = np.array([int(sc.cpu()[0]) for _, sc in bufs])
-    for p in plans:
-        p.close()
+def per_triplet(ts, torch, trips, sample: int, stream, ref_scores=None, spread: bool = False):
+    """The plain per-triplet path on the same GPU: one plan per triplet
+    (inputs resident in HBM), built and warmed untimed, then one timed,
+    synchronised run each; plans are freed one by one, so large triplets
+    never hold their panel faces at the same time. `sample` triplets are
+    taken from the front (or evenly spread over the list)."""
+    idx = (np.linspace(0, len(trips) - 1, min(sample, len(trips))).astype(int) if spread
+           else np.arange(min(sample, len(trips))))
     from paper_2605_28400_amd import synth
-    cells = sum(synth.cells(t) for t in sub)
-    return {"value": round(cells / dt / 1e9, 3), "unit": "GCUPS", "ms": round(dt * 1e3, 3),
-            "sample": f"first {len(sub)} triplets, one plan each, launched back to back",
-            "scores_equal_batched": bool((alone == batch_scores[:len(sub)]).all())}
+    busy, cells, alone = 0.0, 0.0, []
+    for q in idx:
+        t = trips[int(q)]
+        lens, off, words = ts.pack_batch([t])
+        plan = ts.Plan(lens, off)
+        w = torch.from_numpy(words.view(np.int32)).cuda()
+        sc = torch.zeros(1, dtype=torch.int32, device="cuda")
+        plan.run(w, sc, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run(w, sc, stream)
+        torch.cuda.synchronize()
+        busy += time.perf_counter() - t0
+        cells += synth.cells(t)
+        alone.append(int(sc.cpu()[0]))
+        plan.close()
+    rec = {"value": round(cells / busy / 1e9, 3), "unit": "GCUPS", "ms": round(busy * 1e3, 3),
+           "sample": f"{len(idx)} triplets ({'spread over' if spread else 'first of'} {len(trips)}), "
+                     "one plan each, one synchronised launch each"}
+    if ref_scores is not None:
+        rec["scores_equal"] = bool((np.array(alone) == np.asarray(ref_scores)[idx]).all())
+    return rec
 
 
 def served(args):
     """Poisson stream through the continuous-batching server.
 
-    The arrival rate is load x (batched throughput of the same requests
-    scored in one plan) / mean cells per request. Reports sustained GCUPS
-    (cells of completed requests / first submit to last completion) and the
-    submit-to-result latency percentiles.
+    The offered rate is load x the server's closed-loop capacity on these
+    requests (the first ones submitted all at once), in requests per second.
+    Reports sustained GCUPS (cells of all requests / first submit to last
+    result), the submit-to-result latency percentiles, and the plain
+    per-triplet path on a sample of the same requests (whose scores must
+    equal the served ones).
     """
     import torch
     import paper_2605_28400_amd as ts
     from paper_2605_28400_amd import synth
+    print(f"generating {args.requests} requests", file=sys.stderr, flush=True)
     workload, gaps = synth.served_stream(count=args.requests)
     trips = workload.triplets
-    cells = float(workload.total_cells)
-    # Batched throughput of the same requests, as one plan.
-    lens, off, words = ts.pack_batch(trips)
-    plan = ts.Plan(lens, off, use_graph=False)
-    d_words = torch.from_numpy(words.view(np.int32)).cuda()
-    d_scores = torch.zeros(len(trips), dtype=torch.int32, device="cuda")
-    plan.run(d_words, d_scores)
-    torch.cuda.synchronize()
+    cells_each = np.array([synth.cells(t) for t in trips], dtype=np.float64)
+    cells = float(cells_each.sum())
+    max_len = max(max(a.size, b.size, c.size) for a, b, c in trips)
+    budget = 64 << 30
+    # Closed-loop capacity on the first requests.
+    calib = min(len(trips), max(200, len(trips) // 50))
+    srv = ts.Server(max_len=max_len, max_device_bytes=budget)
     t0 = time.perf_counter()
-    plan.run(d_words, d_scores)
-    torch.cuda.synchronize()
-    batch_s = time.perf_counter() - t0
-    batch_scores = d_scores.cpu().numpy()
-    plan.close()
-    batch_gcups = cells / batch_s / 1e9
-    rate = args.load * (cells / batch_s) / (cells / len(trips))  # requests per second
-    srv = ts.Server(max_len=2048, max_device_bytes=96 << 30)
+    cids = [srv.submit(t) for t in trips[:calib]]
+    for rid in cids:
+        srv.wait(rid, timeout_s=600)
+    cap = cells_each[:calib].sum() / (time.perf_counter() - t0)
+    srv.close()
+    rate = args.load * cap / cells_each.mean()
+    print(f"capacity {cap / 1e9:.1f} GCUPS -> offered {rate:.1f} requests/s", file=sys.stderr, flush=True)
+    srv = ts.Server(max_len=max_len, max_device_bytes=budget)
     arrivals = np.cumsum(gaps / rate)
     ids = []
     start = time.perf_counter()
@@ -184,7 +190,7 @@ def served(args):
         if delay > 0:
             time.sleep(delay)
         ids.append(srv.submit(t))
-        if k % 200 == 0:
+        if k % 5000 == 0:
             print(f"submitted {k}/{len(trips)}", file=sys.stderr, flush=True)
     res = {}
     last = 0
@@ -197,17 +203,24 @@ def served(args):
     srv.close()
     served_s = (last - first) * 1e-9
     ok = all(r["status"] == 0 for r in res.values())
-    same = all(res[rid]["score"] == int(batch_scores[k]) for k, rid in enumerate(ids))
+    served_scores = np.array([res[rid]["score"] for rid in ids])
+    stream = torch.cuda.current_stream()
+    alone = per_triplet(ts, torch, trips, args.per_triplet_sample, stream, served_scores, spread=True)
     rec = {
         "metric": "GCUPS", "value": round(cells / served_s / 1e9, 3), "unit": "GCUPS", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": round(served_s * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": workload.name, "requests": len(trips), "cells": int(cells),
                    "seed": workload.seed, "arrivals": "Poisson", "rate_req_per_s": round(rate, 1),
-                   "offered_load": args.load, "parallelism": "single GPU"},
+                   "offered_load": args.load, "closed_loop_capacity_gcups": round(cap / 1e9, 3),
+                   "parallelism": "single GPU"},
         "latency_ms": {"p50": round(st["p50_ns"] / 1e6, 3), "p99": round(st["p99_ns"] / 1e6, 3)},
-        "rounds": st["rounds"], "batched_gcups_same_requests": round(batch_gcups, 3),
-        "all_ok": ok, "served_equals_batched": same,
+        "rounds": st["rounds"], "all_ok": ok, "per_triplet_path": alone,
+        "roofline": {"bound": "alu", "achieved": round(cells * OPS_PER_CELL / served_s / 1e12, 3),
+                     "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOP/s",
+                     "frac": round(cells * OPS_PER_CELL / served_s / 1e12 / PEAK_INT32_TOPS, 4),
+                     "traffic": None, "ops_per_cell": OPS_PER_CELL,
+                     "kernel": "k_sweep rounds (continuous batching), wall clock"},
     }
     print(json.dumps(rec), flush=True)
 

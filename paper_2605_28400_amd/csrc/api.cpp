@@ -96,9 +96,12 @@ DevScoring make_dev_scoring(const trioseq_scoring& sc) {
   return d;
 }
 
-// Triplets with at least this many cells are split into panel jobs when the
-// plan picks engines itself (one wave on 2.5e8 cells takes ~0.1 s).
+// When the plan picks engines itself, a triplet is split into panel jobs if
+// sweeping it whole on one wavefront would hold the launch up: it is alone,
+// it has at least kSplitCells cells (one wave takes ~0.1 s on 2.5e8 cells),
+// or more than kSplitFactor times the batch's mean cells per wavefront.
 const double kSplitCells = 2.5e8;
+const double kSplitFactor = 4.0;
 
 uint64_t panel_steps(const uint32_t l[3], const KernelShape& ks) {
   const uint64_t pj = l[1] / (uint32_t)panel_rows(ks) + 1;
@@ -291,7 +294,8 @@ trioseq_status trioseq_packed_layout(const uint32_t* lens, size_t n, uint64_t* w
 namespace trioseq {
 
 trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
-                            const trioseq_scoring& sc, const trioseq_plan_options& o, Layout* L) {
+                            const trioseq_scoring& sc, const trioseq_plan_options& o, int waves_hint,
+                            Layout* L) {
   if (n && !lens) return fail(TRIOSEQ_ERR_INVALID_ARG, "lens is NULL");
   if (n > (size_t)INT32_MAX) return fail(TRIOSEQ_ERR_TOO_LARGE, "too many triplets");
   trioseq_status st = validate_scoring(&sc);
@@ -322,8 +326,8 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   const int H = panel_rows(ks), W = panel_cols(ks), RR = (int)right_face_row(ks);
 
   // Which triplets are split into panel jobs: forced by the engine option,
-  // else a lone triplet (so it can use the whole GPU) and very large ones
-  // (one wave would take too long on them).
+  // else by the rule at kSplitCells.
+  const double per_wave = cells / std::max(1, waves_hint);
   L->desc.assign(n, TripletDesc{});
   std::vector<char> split(n, 0);
   std::vector<uint64_t> cost(n, 0);
@@ -333,7 +337,8 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   for (size_t t = 0; t < n; ++t) {
     const uint32_t* l = lens + 3 * t;
     const double c = (double)l[0] * l[1] * l[2];
-    const bool sp = o.engine == 1 || (o.engine == -1 && (n == 1 || c >= kSplitCells));
+    const bool sp = o.engine == 1 ||
+                    (o.engine == -1 && (n == 1 || c >= kSplitCells || c > kSplitFactor * per_wave));
     AxisChoice ax = sp ? choose_axes_wide(l) : choose_axes_batch(l, ks);
     TripletDesc& d = L->desc[t];
     for (int a = 0; a < 3; ++a) {
@@ -461,12 +466,20 @@ trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_of
   trioseq_plan_options o{-1, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (!o.tile_rows && !o.tile_cols && !o.waves_per_simd && lens) apply_tuned(lens, n, &o);
+  // Inputs are validated (by the layout) before the device is touched; the
+  // layout is redone if the device's size changes the split rule's hint.
   Layout L;
-  trioseq_status st = build_layout(lens, word_off, n, *scp, o, &L);
+  int hint = 256 * kWavesPerCuHint;
+  trioseq_status st = build_layout(lens, word_off, n, *scp, o, hint, &L);
   if (st != TRIOSEQ_OK) return st;
   DeviceProps dp;
   st = device_props(&dp);
   if (st != TRIOSEQ_OK) return st;
+  if (dp.cus * kWavesPerCuHint != hint) {
+    hint = dp.cus * kWavesPerCuHint;
+    st = build_layout(lens, word_off, n, *scp, o, hint, &L);
+    if (st != TRIOSEQ_OK) return st;
+  }
 
   trioseq_plan* p = new (std::nothrow) trioseq_plan;
   if (!p) return fail(TRIOSEQ_ERR_NOMEM, "plan: host allocation");

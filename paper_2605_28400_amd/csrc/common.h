@@ -71,8 +71,12 @@ struct Layout {
 
 // Validates and lays out n triplets (lens[3t+s], word offsets off[3t+s]).
 // Touches no device state.
+// waves_hint: wavefronts the launch will have (for the split rule).
 trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
-                            const trioseq_scoring& sc, const trioseq_plan_options& o, Layout* L);
+                            const trioseq_scoring& sc, const trioseq_plan_options& o, int waves_hint,
+                            Layout* L);
+// Resident wavefronts per compute unit assumed when sizing the split rule.
+constexpr int kWavesPerCuHint = 8;
 // Autotuning cache keyed by a batch's length profile.
 std::string length_profile(const uint32_t* lens, size_t n);
 void apply_tuned(const uint32_t* lens, size_t n, trioseq_plan_options* o);

@@ -34,7 +34,7 @@
 namespace trioseq {
 namespace {
 
-constexpr int kSlots = 3;
+constexpr int kSlots = 4;
 // Scores are bounded by 2^30 in magnitude, so this value marks "not yet".
 constexpr int32_t kPending = INT32_MIN + 1;
 
@@ -152,7 +152,8 @@ trioseq_status launch_round(trioseq_server* s, Slot& sl, std::vector<Request>& b
   }
   trioseq_plan_options o{-1, s->ks.rj, s->ks.rk, 0, 0, 0};
   Layout& L = *L_out;
-  trioseq_status st = build_layout(lens.data(), offs.data(), n, s->sc, o, &L);
+  trioseq_status st =
+      build_layout(lens.data(), offs.data(), n, s->sc, o, s->dp.cus * kWavesPerCuHint, &L);
   if (st != TRIOSEQ_OK) {
     *err = trioseq_last_error();
     return st;
@@ -356,7 +357,7 @@ trioseq_status trioseq_serve_create(const trioseq_serve_config* cfg, const trios
     const uint32_t lens[3] = {m, m, m};
     Layout L;
     trioseq_plan_options o{-1, s->ks.rj, s->ks.rk, 0, 0, 0};
-    st = build_layout(lens, nullptr, 1, *sc, o, &L);
+    st = build_layout(lens, nullptr, 1, *sc, o, s->dp.cus * kWavesPerCuHint, &L);
     int grid = 0, wpc = 0;
     if (st == TRIOSEQ_OK) st = layout_grid(L, s->dp, 0, &grid, &wpc);
     if (st != TRIOSEQ_OK) {

@@ -115,6 +115,9 @@ struct PanelIO {
 // atomics use); producers never wait, and a consumer whose chunk of entries
 // is not complete yet re-reads the stale ones. Sentinel faces carry the tag
 // kTagAlways, valid in every run.
+// Step of a chunk at which panel jobs issue the next chunk's staging loads.
+constexpr int kWideStageAt = 7;
+
 constexpr int kCohNone = 0;
 constexpr int kCohDevice = 16;              // SC1
 constexpr int kTagAlways = 0x7FFFFFFF;
@@ -393,7 +396,14 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   // the next instruction has overwritten them when the store has an SGPR
   // offset, and the compiler only separates the two for stores without one.
   // Lanes at kOob stay out of range (the chunk base is far below 2^28).
-  auto run_chunk = [&](int c, bool cap) {
+  // Staging loads of chunk c + 1 are issued at step kStageAt of chunk c.
+  // Whole-triplet jobs issue them first (their faces were written long ago,
+  // so only the load latency matters). Panel jobs issue them late, so the
+  // rows they fetch were written as recently as the load latency allows:
+  // every step of prefetch distance would add a step to the lag between a
+  // producer panel and its consumers.
+  constexpr int kStageAt = WIDE ? kWideStageAt : 0;
+  auto run_chunk = [&](int c, bool cap, bool more) {
     const uint32_t cbase = (uint32_t)(c * kChunk);
     const uint32_t vb = vo_bot + cbase * bs, vr = vo_right + cbase * RRB,
                    vc = vo_corner + cbase * RRB;
@@ -404,6 +414,7 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
     const uint8_t* sp = shb + sh_base + c * kChunk;
 #pragma unroll
     for (int s = 0; s < kChunk; ++s) {
+      if (s == kStageAt && more) stage_load(c + 1);
       const int t = c * kChunk + s;
       const uint32_t sh = sp[s];
       int A[RJ], B[RK];
@@ -493,12 +504,9 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
 
   for (int c = 0; c < nchunks; ++c) {
     stage_finish(c);
-    if (c + 1 < nchunks) {
-      stage_load(c + 1);
-    }
     const bool cap_chunk =
         score_out != nullptr && n0 >= c * kChunk - kSkew && n0 <= c * kChunk + kChunk - 1;
-    run_chunk(c, cap_chunk);
+    run_chunk(c, cap_chunk, c + 1 < nchunks);
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
   // System scope: the score may live in mapped host memory (serving), where
