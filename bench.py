@@ -317,6 +317,14 @@ def main():
                      ["whole-triplet jobs", "panel jobs of a split triplet",
                       "whole-triplet and panel jobs"][info["engine"]] + ")"},
     }
+    # End to end through the host API: pack, upload, lay out, sweep, download.
+    ts.score_batch(trips[:1])
+    t0 = time.perf_counter()
+    e2e_scores = ts.score_batch(trips)
+    e2e_s = time.perf_counter() - t0
+    rec["end_to_end"] = {"value": round(cells / e2e_s / 1e9, 3), "unit": "GCUPS",
+                         "ms": round(e2e_s * 1e3, 3), "call": "trioseq_score_batch (host triplets)",
+                         "scores_equal": bool((np.asarray(e2e_scores) == scores).all())}
     if tuned is not None:
         b = tuned["best"]
         rec["config"]["autotuned"] = {"tile": f"{b['tile_rows']}x{b['tile_cols']}",

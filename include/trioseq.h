@@ -80,8 +80,9 @@ trioseq_status trioseq_packed_layout(const uint32_t* lens, size_t n, uint64_t* w
 trioseq_status trioseq_score(const trioseq_triplet* t, const trioseq_scoring* sc, int32_t* score);
 
 /* Scores of n triplets, computed together (one persistent launch for the
- * batch). Synchronous: returns when scores[0..n) (host memory) are written.
- * Work is issued on hip_stream. */
+ * batch; triplets that would hold the launch up are split over many
+ * wavefronts). Synchronous: returns when scores[0..n) (host memory) are
+ * written. Work is issued on hip_stream. */
 trioseq_status trioseq_score_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
                                    int32_t* scores, void* hip_stream);
 

@@ -762,7 +762,7 @@ trioseq_status trioseq_score(const trioseq_triplet* t, const trioseq_scoring* sc
 
 trioseq_status trioseq_score_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
                                    int32_t* scores, void* hip_stream) {
-  return run_host_batch(t, n, sc, scores, (hipStream_t)hip_stream, 0);
+  return run_host_batch(t, n, sc, scores, (hipStream_t)hip_stream, -1);
 }
 
 }  // extern "C"

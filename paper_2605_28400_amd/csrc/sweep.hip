@@ -85,6 +85,7 @@ struct Lds {
   __attribute__((aligned(16))) int sB[64][RK];        // bottom row of each lane
   int sX[64];                                         // bottom of each lane's left halo
   int cap[RJ * RK];                                   // tile of the score cell at slice n0
+  int sink[64];                                       // per-lane discard slot (memory wave)
   int wsync;
 };
 
@@ -148,7 +149,7 @@ __device__ __forceinline__ void stage_shifts(uint8_t* shb, const uint32_t* __res
                                              const TripletDesc& td) {
   const int n0 = (int)td.len[0];
   const int total = n0 + 64;
-  for (int q = threadIdx.x; q < total; q += 64) {
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
     const int i = q - kShiftPre;
     uint32_t v = 0;
     if (i >= 1 && i <= n0) v = residue_at(words, td.off[0], (uint32_t)(i - 1)) << 3;
@@ -158,14 +159,51 @@ __device__ __forceinline__ void stage_shifts(uint8_t* shb, const uint32_t* __res
 }
 
 // One wavefront sweeps one panel over all slices.
-template <int RJ, int RK, bool WIDE>
+// How a panel's halos arrive and its edges leave:
+//  kPlain:    one wavefront; faces in HBM/L2 without tags (whole-triplet
+//             jobs, whose faces the same wave wrote earlier);
+//  kTagged:   one wavefront; tagged faces staged and written by the wave
+//             itself (panel jobs next to whole-triplet jobs);
+//  kSplitCompute: the compute wave of a two-wave panel workgroup: halos come
+//             from LDS rings that the workgroup's memory wave fills, edges go
+//             to LDS rows that the memory wave writes out (panel jobs).
+enum PanelMode { kPlain = 0, kTagged = 1, kSplitCompute = 2 };
+
+// LDS hand-over between the two waves of a panel workgroup. Ring row
+// t mod kRing of the halo rings serves step t; out row t mod kRing holds the
+// edges the compute wave produced at step t. The counters only grow:
+// in_ready = steps whose halo rows are staged (memory wave), out_done =
+// steps computed (compute wave), out_flushed = out rows read back by the
+// memory wave. A wave's LDS operations are performed in order, so a counter
+// written after the rows it covers never runs ahead of them.
+template <int RJ, int RK>
+struct SplitLds {
+  static constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
+  Lds<RJ, RK> L;
+  // Out rows: bottom rows (kRing x W) followed by right rows (kRing x RR).
+  __attribute__((aligned(16))) int out[kRing * (W + RR)];
+  int in_ready, out_done, out_flushed, job;
+  __device__ int* out_bot(int t) { return &out[(t & (kRing - 1)) * W]; }
+  __device__ int* out_right(int t) { return &out[kRing * W + (t & (kRing - 1)) * RR]; }
+};
+
+__device__ __forceinline__ int lds_get(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_put(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int MODE, int RJ, int RK>
 __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring& sc,
                             const uint32_t* __restrict__ words, const TripletDesc& td, int pj, int pk,
-                            const PanelIO& io, int32_t* score_out) {
+                            const PanelIO& io, int32_t* score_out, SplitLds<RJ, RK>* split = nullptr) {
+  constexpr bool WIDE = MODE == kTagged;
+  constexpr bool SPC = MODE == kSplitCompute;
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
   constexpr int COH = WIDE ? kCohDevice : kCohNone;
   constexpr int ES = WIDE ? 2 : 1;  // ints per face entry: value (+ tag)
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int y = lane >> 3, x = lane & 7;
   const int n0 = (int)td.len[0], n1 = (int)td.len[1], n2 = (int)td.len[2];
   const int j0 = pj * H + y * RJ, k0 = pk * W + x * RK;
@@ -364,7 +402,7 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
     }
   };
 
-  stage_load(0);
+  if (!SPC) stage_load(0);
   // Before step 0 the neighbour slots hold slice "-1" for every lane: the
   // sentinel (they are read at step 0, before any lane has written them).
 #pragma unroll
@@ -403,6 +441,8 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   // every step of prefetch distance would add a step to the lag between a
   // producer panel and its consumers.
   constexpr int kStageAt = WIDE ? kWideStageAt : 0;
+  int fin = 0, ffl = 0;  // last read in_ready / out_flushed (split compute wave)
+  bool gave_up = false;
   auto run_chunk = [&](int c, bool cap, bool more) {
     const uint32_t cbase = (uint32_t)(c * kChunk);
     const uint32_t vb = vo_bot + cbase * bs, vr = vo_right + cbase * RRB,
@@ -414,8 +454,34 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
     const uint8_t* sp = shb + sh_base + c * kChunk;
 #pragma unroll
     for (int s = 0; s < kChunk; ++s) {
-      if (s == kStageAt && more) stage_load(c + 1);
+      if (!SPC && s == kStageAt && more) stage_load(c + 1);
       const int t = c * kChunk + s;
+      int fin_next = 0, ffl_next = 0;
+      if (SPC) {
+        // Step t needs its halo rows staged (in_ready > t) and out row
+        // t mod kRing read back (out_flushed > t - kRing). The counters
+        // read during the previous step usually already say so; the reads
+        // for the next step are issued now, behind this step's work.
+        if (!gave_up && !(fin > t && ffl > t - kRing)) {
+          const uint64_t t_start = wall_clock64();
+          for (;;) {
+            fin = lds_get(&split->in_ready);
+            ffl = lds_get(&split->out_flushed);
+            if (fin > t && ffl > t - kRing) break;
+            if (wall_clock64() - t_start > kWaitTicks) {
+              // Give up waiting for the rest of the job (the score is marked
+              // invalid); the job still runs to its end.
+              if (lane == 0) __hip_atomic_store(io.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              gave_up = true;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        fin_next = lds_get(&split->in_ready);
+        ffl_next = lds_get(&split->out_flushed);
+      }
       const uint32_t sh = sp[s];
       int A[RJ], B[RK];
 #pragma unroll
@@ -457,7 +523,23 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
       L.sX[lane] = Lh[RJ - 1];
 
       // Edge stores (the hardware drops lanes whose offset is kOob).
-      if (WIDE) {
+      if (SPC) {
+        if (y == kGJ - 1) {
+          int* ob = split->out_bot(t) + x * RK;
+#pragma unroll
+          for (int cc = 0; cc < RK; ++cc) ob[cc] = N[RJ - 1][cc];
+        }
+        if (x == kGK - 1) {
+          int* orr = split->out_right(t);
+#pragma unroll
+          for (int r = 0; r < RJ; ++r) orr[4 + y * RJ + r] = N[r][RK - 1];
+          if (y == 0) orr[0] = T[RK - 1];
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (lane == 0) lds_put(&split->out_done, t + 1);
+        fin = fin_next;
+        ffl = ffl_next;
+      } else if (WIDE) {
         const int g = io.gen;
 #pragma unroll
         for (int cc = 0; cc < RK; cc += 2)
@@ -503,7 +585,7 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   };
 
   for (int c = 0; c < nchunks; ++c) {
-    stage_finish(c);
+    if (!SPC) stage_finish(c);
     const bool cap_chunk =
         score_out != nullptr && n0 >= c * kChunk - kSkew && n0 <= c * kChunk + kChunk - 1;
     run_chunk(c, cap_chunk, c + 1 < nchunks);
@@ -514,6 +596,228 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   if (own)
     __hip_atomic_store(score_out, L.cap[rsel * RK + csel] + sc.gap2 * (n0 + n1 + n2),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+// The memory wave of a two-wave panel workgroup. It keeps the compute wave's
+// halo rings filled and writes the compute wave's edge rows out:
+//  * staging: for steps u.. it loads, in one batch, top rows u+6 .. u+kChunk+6
+//    and left rows u+7 .. u+kChunk+6 of the producers' tagged faces, finds the
+//    longest run of steps whose needed entries all carry this run's tag
+//    (entries of slices past n0 are never needed), copies them into the ring
+//    rows of those steps (the corner of top lane x >= 1 at step u is entry
+//    x*RK - 1 of top row u+6) and publishes in_ready; a ring row is only
+//    refilled once the compute wave has finished the step kRing earlier;
+//  * flushing: out rows the compute wave has finished are stored as
+//    (value, tag) pairs with device-coherent stores, then out_flushed is
+//    published so the compute wave may reuse those rows.
+// Every
+// wait is bounded: past the wall-clock limit the error flag is raised and
+// the rows are staged as they are, so both waves always finish the job.
+template <int RJ, int RK>
+__device__ void panel_memory(SplitLds<RJ, RK>& S, const TripletDesc& td, const PanelIO& io) {
+  constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
+  constexpr uint32_t ts = W * 8u, RRB = RR * 8u;
+  constexpr int NB = kChunk;
+  constexpr int TOPN = (NB + 1) * W, LEFTN = NB * RR, EPR = W + H + 1;
+  constexpr int QT = (TOPN + 63) / 64, QL = (LEFTN + 63) / 64, QF = (NB * EPR + 63) / 64;
+  static_assert(NB + 1 <= 32, "step masks hold one bit per step of a batch");
+  const int lane = threadIdx.x & 63;
+  const int n0 = (int)td.len[0];
+  const int stepsp = (n0 + 1 + kSkew + kChunk - 1) / kChunk * kChunk;
+  const uint32_t frows = face_rows((uint32_t)n0);
+  const Rsrc r_top = make_rsrc(io.top, (uint64_t)frows * ts);
+  const Rsrc r_left = make_rsrc(io.left, (uint64_t)frows * RRB);
+  const Rsrc r_bot = make_rsrc(io.bot ? io.bot : io.top, io.bot ? (uint64_t)frows * ts : 0);
+  const Rsrc r_right = make_rsrc(io.right ? io.right : io.left, io.right ? (uint64_t)frows * RRB : 0);
+  const int gen = io.gen;
+  // Flat LDS views: out rows (outB then outR), and the halo rings, with a
+  // per-lane sink slot for entries a batch does not publish.
+  const int* outs = S.out;
+  int* sink = &S.L.sink[lane];
+  int staged = 0, flushed = 0;
+  uint64_t stall_since = 0;
+  bool gave_up = false;
+  while (staged < stepsp || flushed < stepsp) {
+    const int done = lds_get(&S.out_done);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    bool progress = false;
+    const int u = staged;
+    const int nb = min(min(NB, stepsp - u), done + kRing - u);
+    if (nb > 0) {
+      v2i tv[QT], lv[QL];
+#pragma unroll
+      for (int q = 0; q < QT; ++q) {
+        const int f = q * 64 + lane;
+        const uint32_t off = f < TOPN ? (uint32_t)(((u + kGJ - 2) * W + f) * 8) : kOob;
+        tv[q] = __builtin_amdgcn_raw_buffer_load_b64(r_top, off, opaque_zero(), kCohDevice);
+      }
+#pragma unroll
+      for (int q = 0; q < QL; ++q) {
+        const int f = q * 64 + lane;
+        const uint32_t off = f < LEFTN ? (uint32_t)(((u + kGK - 1) * RR + f) * 8) : kOob;
+        lv[q] = __builtin_amdgcn_raw_buffer_load_b64(r_left, off, opaque_zero(), kCohDevice);
+      }
+      // Bit k of `bad` is set when step u + k lacks one of this lane's
+      // entries (a stale tag on an entry of a slice <= n0).
+      uint32_t bad = 0;
+#pragma unroll
+      for (int q = 0; q < QT; ++q) {
+        const int f = q * 64 + lane;
+        const int rr = f / W, e = f % W, x = e / RK;  // top row u + 6 + rr
+        const bool stale = f < TOPN && u + rr - 1 - x <= n0 && tv[q].y < gen;
+        const bool corner = e % RK == RK - 1 && x + 1 < kGK;
+        bad |= stale ? ((rr >= 1 ? 1u << (rr - 1) : 0u) | (corner ? 1u << rr : 0u)) : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < QL; ++q) {
+        const int f = q * 64 + lane;
+        const int rr = f / RR, e = f % RR;  // left row u + 7 + rr
+        const int slice = u + rr - (e == 0 ? 0 : (e - 4) / RJ);
+        const bool stale = f < LEFTN && (e == 0 || e >= 4) && slice <= n0 && lv[q].y < gen;
+        bad |= stale ? 1u << rr : 0u;
+      }
+      int k = nb;
+#pragma unroll
+      for (int b = NB - 1; b >= 0; --b)
+        if (__builtin_amdgcn_ballot_w64((bad >> b) & 1u) != 0) k = b;
+      k = min(k, nb);
+      if (gave_up) k = nb;
+      if (k <= 0 && stall_since && wall_clock64() - stall_since > kWaitTicks) {
+        // Stop waiting for producers for the rest of the job (the score is
+        // marked invalid) so that both waves finish it.
+        if (lane == 0) __hip_atomic_store(io.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        gave_up = true;
+        k = nb;
+      }
+      if (k > 0) {
+        const int hi = u + k;
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+          const int f = q * 64 + lane;
+          const int rr = f / W, e = f % W, x = e / RK;
+          const int st = u + rr - 1, sc = u + rr;  // T row of step st, corner row of step sc
+          int* dt = (f < TOPN && st >= u && st < hi) ? &S.L.ringT[st & (kRing - 1)][e] : sink;
+          *dt = tv[q].x;
+          int* dc = (f < TOPN && e % RK == RK - 1 && x + 1 < kGK && sc < hi)
+                        ? &S.L.ringC[sc & (kRing - 1)][(x + 1) & (kGK - 1)]
+                        : sink;
+          *dc = tv[q].x;
+        }
+#pragma unroll
+        for (int q = 0; q < QL; ++q) {
+          const int f = q * 64 + lane;
+          const int rr = f / RR, e = f % RR;
+          const int st = u + rr;
+          int* dl = !(f < LEFTN && st < hi) ? sink
+                    : e == 0                 ? &S.L.ringC[st & (kRing - 1)][0]
+                    : e >= 4                 ? &S.L.ringL[st & (kRing - 1)][e - 4]
+                                             : sink;
+          *dl = lv[q].x;
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (lane == 0) lds_put(&S.in_ready, hi);
+        staged = hi;
+        progress = true;
+      }
+    }
+    // Flush finished out rows (entries per row: W bottom, the corner, H
+    // right). Issued after the staging loads were consumed, so the stores
+    // drain while the next batch's loads are in flight.
+    const int nf = min(NB, lds_get(&S.out_done) - flushed);
+    if (nf > 0) {
+      int v[QF];
+      uint32_t ob[QF], orr[QF];
+#pragma unroll
+      for (int q = 0; q < QF; ++q) {
+        const int f = q * 64 + lane;
+        const int row = f / EPR, e = f % EPR;
+        const int t = flushed + row, ro = t & (kRing - 1);
+        const int er = e == W ? 0 : 4 + (e - W - 1);  // right-face entry
+        v[q] = outs[e < W ? ro * W + e : kRing * W + ro * RR + er];
+        const bool live = row < nf;
+        ob[q] = live && e < W ? (uint32_t)((t * W + e) * 8) : kOob;
+        orr[q] = live && e >= W ? (uint32_t)((t * RR + er) * 8) : kOob;
+      }
+#pragma unroll
+      for (int q = 0; q < QF; ++q) {
+        __builtin_amdgcn_raw_buffer_store_b64((v2i){v[q], gen}, r_bot, ob[q], 0, kCohDevice);
+        __builtin_amdgcn_raw_buffer_store_b64((v2i){v[q], gen}, r_right, orr[q], 0, kCohDevice);
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (lane == 0) lds_put(&S.out_flushed, flushed + nf);
+      flushed += nf;
+      progress = true;
+    }
+    if (progress) {
+      stall_since = 0;
+    } else {
+      if (!stall_since) stall_since = wall_clock64();
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+}
+
+// Panel jobs on two-wave workgroups: wave 0 computes (kSplitCompute), wave 1
+// moves faces (panel_memory). The workgroup pops jobs from the same queue
+// and in the same dependency order as k_sweep, so the same residency
+// argument holds: every producer was popped earlier by a running workgroup.
+template <int RJ, int RK, int WPE>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE))) k_panel(SweepArgs a) {
+  constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
+  __shared__ SplitLds<RJ, RK> S;
+  extern __shared__ uint8_t shb[];
+  const int wave = threadIdx.x >> 6;
+  const int gen = __hip_atomic_load(a.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t staged = 0xFFFFFFFFu;
+  for (;;) {
+    if (threadIdx.x == 0) S.job = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int idx = S.job;
+    if (idx >= (int)a.njobs) break;
+    const JobDesc jd = a.jobs[idx];
+    const TripletDesc td = a.desc[jd.trip];
+    if (jd.trip != staged) {
+      stage_shifts(shb, a.words, td);
+      staged = jd.trip;
+    }
+    if (threadIdx.x == 0) {
+      S.in_ready = 0;
+      S.out_done = 0;
+      S.out_flushed = 0;
+    }
+    __syncthreads();
+    const int n1 = (int)td.len[1], n2 = (int)td.len[2];
+    const int PJ = n1 / H + 1, PK = n2 / W + 1;
+    const uint64_t rows = face_rows(td.len[0]);
+    const uint32_t p = jd.panel;
+    const int pj = (int)(p / (uint32_t)PK), pk = (int)(p % (uint32_t)PK);
+    const uint64_t fb_ints = rows * W * 2;
+    const uint64_t per_panel = fb_ints + rows * RR * 2;
+    int* pool = a.pface + td.face_off;
+    int* base = pool + (uint64_t)p * per_panel;
+    PanelIO io;
+    io.top = pj ? pool + (uint64_t)(p - PK) * per_panel : (pk ? a.bnd_tagged[1] : a.bnd_tagged[0]);
+    io.left = pk ? pool + (uint64_t)(p - 1) * per_panel + fb_ints : a.bnd_tagged[2];
+    io.bot = pj + 1 < PJ ? base : nullptr;
+    io.right = pk + 1 < PK ? base + fb_ints : nullptr;
+    io.gen = gen;
+    io.err = a.ctl + 1;
+    int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
+    if (wave == 0)
+      sweep_panel<kSplitCompute, RJ, RK>(S.L, shb, a.sc, a.words, td, pj, pk, io, so, &S);
+    else
+      panel_memory<RJ, RK>(S, td, io);
+    __syncthreads();
+    if (so && threadIdx.x == 0 &&
+        __hip_atomic_load(io.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+      __hip_atomic_store(so, INT32_MIN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // The persistent scoring kernel. Waves pop jobs from a device queue in
@@ -565,7 +869,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
           io.gen = 0;
           io.err = nullptr;
           int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
-          sweep_panel<RJ, RK, false>(L, shb, a.sc, a.words, td, pj, pk, io, so);
+          sweep_panel<kPlain, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk, io, so);
         }
       }
     } else if (MODES & 2) {
@@ -583,7 +887,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       io.gen = gen;
       io.err = a.ctl + 1;
       int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
-      sweep_panel<RJ, RK, true>(L, shb, a.sc, a.words, td, pj, pk, io, so);
+      sweep_panel<kTagged, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk, io, so);
       if (so && threadIdx.x == 0 &&
           __hip_atomic_load(io.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
         __hip_atomic_store(so, INT32_MIN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -656,7 +960,10 @@ hipError_t launch_sweep(const KernelShape& ks, int modes, const SweepArgs& a, in
   const size_t lds = shift_lds_bytes(a.lds_n0);
 #define Y(r, c, w, m)                                                                  \
   if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m) {                         \
-    hipLaunchKernelGGL((k_sweep<r, c, w, m>), dim3(grid), dim3(64), lds, s, a);        \
+    if (m == 2)                                                                        \
+      hipLaunchKernelGGL((k_panel<r, c, w>), dim3(grid), dim3(128), lds, s, a);        \
+    else                                                                               \
+      hipLaunchKernelGGL((k_sweep<r, c, w, m>), dim3(grid), dim3(64), lds, s, a);      \
     return hipGetLastError();                                                          \
   }
 #define X(r, c, w) TRIOSEQ_MODES(Y, r, c, w)
@@ -667,10 +974,12 @@ hipError_t launch_sweep(const KernelShape& ks, int modes, const SweepArgs& a, in
 }
 
 hipError_t sweep_occupancy(const KernelShape& ks, int modes, uint32_t lds_n0, int* waves_per_cu) {
-#define Y(r, c, w, m)                                                                         \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m)                                  \
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_sweep<r, c, w, m>, 64, \
-                                                        shift_lds_bytes(lds_n0));
+#define Y(r, c, w, m)                                                                          \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m)                                   \
+    return m == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_panel<r, c, w>, \
+                                                                 128, shift_lds_bytes(lds_n0))   \
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_sweep<r, c, w, m>, \
+                                                                 64, shift_lds_bytes(lds_n0));
 #define X(r, c, w) TRIOSEQ_MODES(Y, r, c, w)
   TRIOSEQ_SHAPES(X)
 #undef X
