@@ -452,6 +452,11 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
     const int* cb = c_base + rr * c_str;
     const int* lb = l_base + rr * l_str;
     const uint8_t* sp = shb + sh_base + c * kChunk;
+    // The chunk's lookup shifts, read together: one LDS round trip per chunk
+    // instead of one per step ahead of the halo reads.
+    uint32_t shv[kChunk];
+#pragma unroll
+    for (int s = 0; s < kChunk; ++s) shv[s] = sp[s];
 #pragma unroll
     for (int s = 0; s < kChunk; ++s) {
       if (!SPC && s == kStageAt && more) stage_load(c + 1);
@@ -482,7 +487,7 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
         fin_next = lds_get(&split->in_ready);
         ffl_next = lds_get(&split->out_flushed);
       }
-      const uint32_t sh = sp[s];
+      const uint32_t sh = shv[s];
       int A[RJ], B[RK];
 #pragma unroll
       for (int r = 0; r < RJ; ++r) A[r] = sbyte(TB[r], sh);
