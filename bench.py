@@ -35,8 +35,9 @@ WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served")
 # with the commands are under profiles/). Each figure holds only for the kernel
 # source it was measured on; for any other source the field is null.
 TRAFFIC = {
-    "single_1024x1000x1048": (2.0975e9, "0247fbc75818dfc9"),
-    "batch_8192_len100-400": (1.5054e11, "0247fbc75818dfc9"),
+    "single_1024x1000x1048": (1.5629e9, "330a41ad2001568d"),
+    "batch_8192_len100-400": (7.2385e10, "330a41ad2001568d"),
+    "single_4096x4000x4150": (7.8966e10, "330a41ad2001568d"),
 }
 
 
@@ -313,9 +314,9 @@ def main():
                      "frac": round(achieved / PEAK_INT32_TOPS, 4),
                      "traffic": measured_traffic(workload.name),
                      "kernel_ms": round(ms_events, 4), "ops_per_cell": OPS_PER_CELL,
-                     "kernel": "k_sweep (persistent job queue: " +
-                     ["whole-triplet jobs", "panel jobs of a split triplet",
-                      "whole-triplet and panel jobs"][info["engine"]] + ")"},
+                     "kernel": ["k_sweep (persistent job queue, whole-triplet jobs)",
+                                "k_panel (persistent job queue, two-wave panel workgroups)",
+                                "k_sweep (persistent job queue, whole-triplet and panel jobs)"][info["engine"]]},
     }
     # End to end through the host API: pack, upload, lay out, sweep, download.
     ts.score_batch(trips[:1])
