@@ -503,21 +503,52 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
       const int corner = cb[s * c_str];
 
       int N[RJ][RK];
+      if (RJ * RK <= 16) {
+        // Candidates from the previous slice only (the moves that consume
+        // S0's residue), computed while the halo reads are in flight: Q = the
+        // best of the single move along S0 and its two double moves, X7 the
+        // triple move. (Larger tiles keep the fused form below: holding Q and
+        // X7 for every cell would spill their registers.)
+        int Q[RJ][RK], X7[RJ][RK];
 #pragma unroll
-      for (int r = 0; r < RJ; ++r) {
+        for (int r = 0; r < RJ; ++r) {
 #pragma unroll
-        for (int cc = 0; cc < RK; ++cc) {
-          const int up_cur = r ? N[r - 1][cc] : T[cc];
-          const int up_prev = r ? P[r - 1][cc] : Tp[cc];
-          const int left_cur = cc ? N[r][cc - 1] : Lh[r];
-          const int left_prev = cc ? P[r][cc - 1] : Lp[r];
-          const int diag_cur = r ? (cc ? N[r - 1][cc - 1] : Lh[r - 1]) : (cc ? T[cc - 1] : corner);
-          const int x4 = up_prev + A[r];
-          const int x5 = left_prev + B[cc];
-          const int x6 = diag_cur + (int)(int8_t)(uint8_t)(Cp[r][cc >> 2] >> (8 * (cc & 3)));
-          const int x7 = D[r][cc] + A[r] + B[cc];
-          N[r][cc] = max3i(max3i(P[r][cc], up_cur, left_cur), max3i(x4, x5, x6), x7);
-          D[r][cc] = x6;
+          for (int cc = 0; cc < RK; ++cc) {
+            const int up_prev = r ? P[r - 1][cc] : Tp[cc];
+            const int left_prev = cc ? P[r][cc - 1] : Lp[r];
+            Q[r][cc] = max3i(P[r][cc], up_prev + A[r], left_prev + B[cc]);
+            X7[r][cc] = D[r][cc] + A[r] + B[cc];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < RJ; ++r) {
+#pragma unroll
+          for (int cc = 0; cc < RK; ++cc) {
+            const int up_cur = r ? N[r - 1][cc] : T[cc];
+            const int left_cur = cc ? N[r][cc - 1] : Lh[r];
+            const int diag_cur = r ? (cc ? N[r - 1][cc - 1] : Lh[r - 1]) : (cc ? T[cc - 1] : corner);
+            const int x6 = diag_cur + (int)(int8_t)(uint8_t)(Cp[r][cc >> 2] >> (8 * (cc & 3)));
+            N[r][cc] = max3i(max3i(Q[r][cc], X7[r][cc], x6), up_cur, left_cur);
+            D[r][cc] = x6;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < RJ; ++r) {
+#pragma unroll
+          for (int cc = 0; cc < RK; ++cc) {
+            const int up_cur = r ? N[r - 1][cc] : T[cc];
+            const int up_prev = r ? P[r - 1][cc] : Tp[cc];
+            const int left_cur = cc ? N[r][cc - 1] : Lh[r];
+            const int left_prev = cc ? P[r][cc - 1] : Lp[r];
+            const int diag_cur = r ? (cc ? N[r - 1][cc - 1] : Lh[r - 1]) : (cc ? T[cc - 1] : corner);
+            const int x4 = up_prev + A[r];
+            const int x5 = left_prev + B[cc];
+            const int x6 = diag_cur + (int)(int8_t)(uint8_t)(Cp[r][cc >> 2] >> (8 * (cc & 3)));
+            const int x7 = D[r][cc] + A[r] + B[cc];
+            N[r][cc] = max3i(max3i(P[r][cc], up_cur, left_cur), max3i(x4, x5, x6), x7);
+            D[r][cc] = x6;
+          }
         }
       }
 
