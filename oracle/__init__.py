@@ -1,4 +1,4 @@
-"""CPU oracle for exact global 3-way alignment scoring (test infrastructure).
+"""CPU oracle for exact 3-way alignment scoring, global and local (test infrastructure).
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg use
 this package. The library never imports it, and it imports nothing from the
@@ -42,8 +42,10 @@ def _load():
         lib.oracle_score.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, u8p,
                                      ctypes.c_int64, i32p, ctypes.c_int32, i64p]
         lib.oracle_score.restype = ctypes.c_int
+        lib.oracle_score_local.argtypes = lib.oracle_score.argtypes
+        lib.oracle_score_local.restype = ctypes.c_int
         lib.oracle_score_batch.argtypes = [u8p, i64p, i64p, ctypes.c_int64, i32p,
-                                           ctypes.c_int32, i64p, ctypes.c_int]
+                                           ctypes.c_int32, i64p, ctypes.c_int, ctypes.c_int]
         lib.oracle_score_batch.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -67,13 +69,19 @@ def _u8(a):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
 
 
-def score(triplet, sub=DEFAULT_SUB, gap: int = DEFAULT_GAP) -> int:
-    """Optimal global sum-of-pairs score M[a][b][c] of one triplet of codes 0..3."""
+# Alignment kinds (the paper's Section II variants implemented here).
+GLOBAL, LOCAL = 0, 2
+
+
+def score(triplet, sub=DEFAULT_SUB, gap: int = DEFAULT_GAP, kind: int = GLOBAL) -> int:
+    """Optimal sum-of-pairs score of one triplet of codes 0..3: M[a][b][c]
+    (global) or the largest value of the local tensor (local)."""
     lib = _load()
+    fn = lib.oracle_score_local if kind == LOCAL else lib.oracle_score
     keep = [_u8(s) for s in triplet]
     sub = np.ascontiguousarray(sub, dtype=np.int32).reshape(16)
     out = ctypes.c_int64()
-    rc = lib.oracle_score(keep[0][1], keep[0][0].size, keep[1][1], keep[1][0].size,
+    rc = fn(keep[0][1], keep[0][0].size, keep[1][1], keep[1][0].size,
                           keep[2][1], keep[2][0].size,
                           sub.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(gap),
                           ctypes.byref(out))
@@ -82,7 +90,8 @@ def score(triplet, sub=DEFAULT_SUB, gap: int = DEFAULT_GAP) -> int:
     return int(out.value)
 
 
-def score_batch(triplets, sub=DEFAULT_SUB, gap: int = DEFAULT_GAP, threads: int | None = None):
+def score_batch(triplets, sub=DEFAULT_SUB, gap: int = DEFAULT_GAP, threads: int | None = None,
+                kind: int = GLOBAL):
     """Scores of many triplets, one triplet per thread at a time."""
     lib = _load()
     n = len(triplets)
@@ -101,7 +110,7 @@ def score_batch(triplets, sub=DEFAULT_SUB, gap: int = DEFAULT_GAP, threads: int 
     rc = lib.oracle_score_batch(seqs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                 off.ctypes.data_as(i64p), lens.ctypes.data_as(i64p), n,
                                 sub.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(gap),
-                                out.ctypes.data_as(i64p), int(threads))
+                                out.ctypes.data_as(i64p), int(threads), int(kind))
     if rc != 0:
         raise MemoryError("oracle could not allocate its slices")
     return out[:n]

@@ -1,5 +1,5 @@
 /*
- * CPU oracle for exact global 3-way alignment scoring.
+ * CPU oracle for exact 3-way alignment scoring (global and local).
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the library or its Python binding
  * links, loads or calls this file; only the test-suite, the smoke check and
@@ -110,6 +110,78 @@ int oracle_score(const uint8_t *s0, int64_t a, const uint8_t *s1, int64_t b,
     return 0;
 }
 
+/*
+ * Local variant (paper, Section II, "Local Alignments"): the initialisation of
+ * the semi-global variant (M[i][0][0] = M[0][j][0] = M[0][0][k] = 0) with
+ * v = 0 as an eighth candidate of Eq. 1 for every cell, so no value is
+ * negative; an alignment may start and end anywhere, and the score is the
+ * largest value anywhere in the tensor. With v = 0 in every cell the axis
+ * values are max(0, moves) = 0 for a non-positive gap, which is the stated
+ * initialisation; the recurrence below applies v = 0 to every cell, axes
+ * included. Same int64 two-slice loop as oracle_score.
+ */
+int oracle_score_local(const uint8_t *s0, int64_t a, const uint8_t *s1, int64_t b,
+                       const uint8_t *s2, int64_t c, const int32_t *sub, int32_t gap,
+                       int64_t *out)
+{
+    const int64_t w = c + 1;
+    int64_t *last = (int64_t *)malloc((size_t)((b + 1) * w) * sizeof(int64_t));
+    int64_t *here = (int64_t *)malloc((size_t)((b + 1) * w) * sizeof(int64_t));
+    if (!last || !here) {
+        free(last);
+        free(here);
+        return -1;
+    }
+    const int64_t twogap = 2 * (int64_t)gap; /* a residue against two gaps */
+    int64_t top = 0;
+    for (int64_t i = 0; i <= a; i++) {
+        for (int64_t j = 0; j <= b; j++) {
+            for (int64_t k = 0; k <= c; k++) {
+                const int x = i > 0 ? s0[i - 1] : 0, y = j > 0 ? s1[j - 1] : 0, z = k > 0 ? s2[k - 1] : 0;
+                int64_t m = 0; /* v = 0: the eighth candidate */
+                int64_t cand;
+                if (i && j && k) {
+                    cand = last[(j - 1) * w + k - 1] + (pair(sub, x, y) + pair(sub, x, z)) + pair(sub, y, z);
+                    m = cand > m ? cand : m;
+                }
+                if (i && j) {
+                    cand = last[(j - 1) * w + k] + pair(sub, x, y) + twogap;
+                    m = cand > m ? cand : m;
+                }
+                if (i && k) {
+                    cand = last[j * w + k - 1] + pair(sub, x, z) + twogap;
+                    m = cand > m ? cand : m;
+                }
+                if (j && k) {
+                    cand = here[(j - 1) * w + k - 1] + pair(sub, y, z) + twogap;
+                    m = cand > m ? cand : m;
+                }
+                if (i) {
+                    cand = last[j * w + k] + twogap;
+                    m = cand > m ? cand : m;
+                }
+                if (j) {
+                    cand = here[(j - 1) * w + k] + twogap;
+                    m = cand > m ? cand : m;
+                }
+                if (k) {
+                    cand = here[j * w + k - 1] + twogap;
+                    m = cand > m ? cand : m;
+                }
+                here[j * w + k] = m;
+                top = m > top ? m : top;
+            }
+        }
+        int64_t *t = last;
+        last = here;
+        here = t;
+    }
+    *out = top;
+    free(last);
+    free(here);
+    return 0;
+}
+
 /* Many triplets on a pool of plain threads, one triplet at a time each.
  * seqs holds all residues back to back; off[3*t+s] / len[3*t+s] locate
  * sequence s of triplet t. */
@@ -120,6 +192,7 @@ typedef struct {
     int64_t n;
     const int32_t *sub;
     int32_t gap;
+    int kind; /* 0 global, 2 local */
     int64_t *out;
     int64_t next;
     int failed;
@@ -135,8 +208,12 @@ static void *batch_worker(void *arg)
         pthread_mutex_unlock(&job->lock);
         if (t >= job->n) return NULL;
         const int64_t *o = job->off + 3 * t, *l = job->len + 3 * t;
-        if (oracle_score(job->seqs + o[0], l[0], job->seqs + o[1], l[1], job->seqs + o[2], l[2],
-                         job->sub, job->gap, job->out + t) != 0) {
+        int rc = job->kind == 2
+                     ? oracle_score_local(job->seqs + o[0], l[0], job->seqs + o[1], l[1],
+                                          job->seqs + o[2], l[2], job->sub, job->gap, job->out + t)
+                     : oracle_score(job->seqs + o[0], l[0], job->seqs + o[1], l[1], job->seqs + o[2],
+                                    l[2], job->sub, job->gap, job->out + t);
+        if (rc != 0) {
             pthread_mutex_lock(&job->lock);
             job->failed = 1;
             pthread_mutex_unlock(&job->lock);
@@ -145,7 +222,7 @@ static void *batch_worker(void *arg)
 }
 
 int oracle_score_batch(const uint8_t *seqs, const int64_t *off, const int64_t *len, int64_t n,
-                       const int32_t *sub, int32_t gap, int64_t *out, int threads)
+                       const int32_t *sub, int32_t gap, int64_t *out, int threads, int kind)
 {
     batch_job job;
     memset(&job, 0, sizeof job);
@@ -155,6 +232,7 @@ int oracle_score_batch(const uint8_t *seqs, const int64_t *off, const int64_t *l
     job.n = n;
     job.sub = sub;
     job.gap = gap;
+    job.kind = kind;
     job.out = out;
     pthread_mutex_init(&job.lock, NULL);
     if (threads < 1) threads = 1;

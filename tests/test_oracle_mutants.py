@@ -88,3 +88,69 @@ def test_unmodified_source_passes(tmp_path):
 def test_mutant_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     assert not _pins_pass(_build(tmp_path, name, old, new))
+
+
+# Planted mistakes in the local variant, caught by its own pins (brute force
+# over substring triples, identical sequences).
+LOCAL_MUTANTS = {
+    "local_no_zero_floor": ("int64_t m = 0; /* v = 0: the eighth candidate */",
+                            "int64_t m = i + j + k ? -4000000 : 0;"),
+    "local_score_not_tracked": ("top = m > top ? m : top;", "top = top;"),
+    "local_single_gap_once": ("const int64_t twogap = 2 * (int64_t)gap;",
+                              "const int64_t twogap = (int64_t)gap;"),
+    "local_jk_move_from_last_slice": (
+        "cand = here[(j - 1) * w + k - 1] + pair(sub, y, z) + twogap;",
+        "cand = last[(j - 1) * w + k - 1] + pair(sub, y, z) + twogap;"),
+    "local_drop_triple_move": (
+        "cand = last[(j - 1) * w + k - 1] + (pair(sub, x, y) + pair(sub, x, z)) + pair(sub, y, z);",
+        "cand = -4000000;"),
+}
+
+
+def _build_local(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / f"{name}.so"
+    subprocess.run(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-pthread", "-o", str(so),
+                    str(path)], check=True)
+    lib = ctypes.CDLL(str(so))
+    u8p, i32p, i64p = (ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
+                       ctypes.POINTER(ctypes.c_int64))
+    lib.oracle_score_local.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, u8p,
+                                       ctypes.c_int64, i32p, ctypes.c_int32, i64p]
+
+    def score(trip, sub, gap):
+        arrs = [np.ascontiguousarray(s, np.uint8) for s in trip]
+        sub = np.ascontiguousarray(sub, np.int32).reshape(16)
+        out = ctypes.c_int64()
+        lib.oracle_score_local(*[x for a in arrs for x in (a.ctypes.data_as(u8p), a.size)],
+                               sub.ctypes.data_as(i32p), gap, ctypes.byref(out))
+        return out.value
+
+    return score
+
+
+def _local_pins_pass(score) -> bool:
+    from tests.test_oracle_local import local_brute
+    rng = np.random.default_rng(4321)
+    memo = {}
+    for trial in range(30):
+        trip = [rng.integers(0, 4, size=int(n)).astype(np.uint8) for n in rng.integers(0, 3, 3)]
+        sub = oracle.DEFAULT_SUB if trial % 2 else pins.random_symmetric_sub(rng)
+        if score(trip, sub, -2) != local_brute(trip, sub, -2, memo):
+            return False
+    x = rng.integers(0, 4, size=9).astype(np.uint8)
+    return score([x, x, x], oracle.DEFAULT_SUB, -2) == 27
+
+
+def test_unmodified_local_source_passes(tmp_path):
+    assert _local_pins_pass(_build_local(tmp_path, "local_identity", "top = m > top ? m : top;",
+                                         "top = m > top ? m : top;"))
+
+
+@pytest.mark.parametrize("name", sorted(LOCAL_MUTANTS))
+def test_local_mutant_is_caught(tmp_path, name):
+    old, new = LOCAL_MUTANTS[name]
+    assert not _local_pins_pass(_build_local(tmp_path, name, old, new))
