@@ -1,4 +1,5 @@
-"""CPU oracle for exact 3-way alignment scoring, global and local (test infrastructure).
+"""CPU oracle for exact 3-way alignment scoring, global, semi-global and local
+(test infrastructure).
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg use
 this package. The library never imports it, and it imports nothing from the
@@ -44,6 +45,8 @@ def _load():
         lib.oracle_score.restype = ctypes.c_int
         lib.oracle_score_local.argtypes = lib.oracle_score.argtypes
         lib.oracle_score_local.restype = ctypes.c_int
+        lib.oracle_score_semiglobal.argtypes = lib.oracle_score.argtypes
+        lib.oracle_score_semiglobal.restype = ctypes.c_int
         lib.oracle_score_batch.argtypes = [u8p, i64p, i64p, ctypes.c_int64, i32p,
                                            ctypes.c_int32, i64p, ctypes.c_int, ctypes.c_int]
         lib.oracle_score_batch.restype = ctypes.c_int
@@ -70,14 +73,16 @@ def _u8(a):
 
 
 # Alignment kinds (the paper's Section II variants implemented here).
-GLOBAL, LOCAL = 0, 2
+GLOBAL, SEMI_GLOBAL, LOCAL = 0, 1, 2
 
 
 def score(triplet, sub=DEFAULT_SUB, gap: int = DEFAULT_GAP, kind: int = GLOBAL) -> int:
     """Optimal sum-of-pairs score of one triplet of codes 0..3: M[a][b][c]
-    (global) or the largest value of the local tensor (local)."""
+    (global), the best cell on the last slices (semi-global) or the largest
+    value of the local tensor (local)."""
     lib = _load()
-    fn = lib.oracle_score_local if kind == LOCAL else lib.oracle_score
+    fn = {GLOBAL: lib.oracle_score, SEMI_GLOBAL: lib.oracle_score_semiglobal,
+          LOCAL: lib.oracle_score_local}[kind]
     keep = [_u8(s) for s in triplet]
     sub = np.ascontiguousarray(sub, dtype=np.int32).reshape(16)
     out = ctypes.c_int64()

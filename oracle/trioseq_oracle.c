@@ -1,5 +1,5 @@
 /*
- * CPU oracle for exact 3-way alignment scoring (global and local).
+ * CPU oracle for exact 3-way alignment scoring (global, semi-global and local).
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the library or its Python binding
  * links, loads or calls this file; only the test-suite, the smoke check and
@@ -111,6 +111,81 @@ int oracle_score(const uint8_t *s0, int64_t a, const uint8_t *s1, int64_t b,
 }
 
 /*
+ * Semi-global variant (paper, Section II, "Semi-Global Alignments"): v stays
+ * -infinity (a move with a negative predecessor index does not exist), the
+ * three axes are set to 0 (M[i][0][0] = M[0][j][0] = M[0][0][k] = 0, whatever
+ * the moves along them would give), every other cell follows Eq. 1, and the
+ * score is the largest value on the last slices i = a, j = b or k = c.
+ * Same int64 two-slice loop as oracle_score.
+ */
+int oracle_score_semiglobal(const uint8_t *s0, int64_t a, const uint8_t *s1, int64_t b,
+                            const uint8_t *s2, int64_t c, const int32_t *sub, int32_t gap,
+                            int64_t *out)
+{
+    const int64_t stride = c + 1;
+    int64_t *older = (int64_t *)malloc((size_t)((b + 1) * stride) * sizeof(int64_t));
+    int64_t *newer = (int64_t *)malloc((size_t)((b + 1) * stride) * sizeof(int64_t));
+    if (!older || !newer) {
+        free(older);
+        free(newer);
+        return -1;
+    }
+    const int64_t gg = 2 * (int64_t)gap; /* one residue and two gaps */
+    int64_t answer = NEG_INF;
+    for (int64_t i = 0; i <= a; i++) {
+        for (int64_t j = 0; j <= b; j++) {
+            for (int64_t k = 0; k <= c; k++) {
+                int64_t m;
+                if ((i == 0) + (j == 0) + (k == 0) >= 2) {
+                    m = 0; /* an axis */
+                } else {
+                    const int x = i ? s0[i - 1] : 0, y = j ? s1[j - 1] : 0, z = k ? s2[k - 1] : 0;
+                    m = NEG_INF;
+                    int64_t t;
+                    if (i && j && k) {
+                        t = older[(j - 1) * stride + (k - 1)] + pair(sub, y, z) + pair(sub, x, y) + pair(sub, x, z);
+                        if (t > m) m = t;
+                    }
+                    if (j && k) {
+                        t = newer[(j - 1) * stride + (k - 1)] + gg + pair(sub, y, z);
+                        if (t > m) m = t;
+                    }
+                    if (i && k) {
+                        t = older[j * stride + (k - 1)] + gg + pair(sub, x, z);
+                        if (t > m) m = t;
+                    }
+                    if (i && j) {
+                        t = older[(j - 1) * stride + k] + gg + pair(sub, x, y);
+                        if (t > m) m = t;
+                    }
+                    if (k) {
+                        t = newer[j * stride + (k - 1)] + gg;
+                        if (t > m) m = t;
+                    }
+                    if (j) {
+                        t = newer[(j - 1) * stride + k] + gg;
+                        if (t > m) m = t;
+                    }
+                    if (i) {
+                        t = older[j * stride + k] + gg;
+                        if (t > m) m = t;
+                    }
+                }
+                newer[j * stride + k] = m;
+                if ((i == a || j == b || k == c) && m > answer) answer = m;
+            }
+        }
+        int64_t *sw = older;
+        older = newer;
+        newer = sw;
+    }
+    *out = answer;
+    free(older);
+    free(newer);
+    return 0;
+}
+
+/*
  * Local variant (paper, Section II, "Local Alignments"): the initialisation of
  * the semi-global variant (M[i][0][0] = M[0][j][0] = M[0][0][k] = 0) with
  * v = 0 as an eighth candidate of Eq. 1 for every cell, so no value is
@@ -211,6 +286,9 @@ static void *batch_worker(void *arg)
         int rc = job->kind == 2
                      ? oracle_score_local(job->seqs + o[0], l[0], job->seqs + o[1], l[1],
                                           job->seqs + o[2], l[2], job->sub, job->gap, job->out + t)
+                 : job->kind == 1
+                     ? oracle_score_semiglobal(job->seqs + o[0], l[0], job->seqs + o[1], l[1],
+                                               job->seqs + o[2], l[2], job->sub, job->gap, job->out + t)
                      : oracle_score(job->seqs + o[0], l[0], job->seqs + o[1], l[1], job->seqs + o[2],
                                     l[2], job->sub, job->gap, job->out + t);
         if (rc != 0) {

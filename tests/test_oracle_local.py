@@ -27,7 +27,7 @@ def local_brute(trip, sub, gap, memo):
     for a in substrings(trip[0]):
         for b in substrings(trip[1]):
             for c in substrings(trip[2]):
-                key = (a, b, c, id(sub), gap)
+                key = (a, b, c, np.asarray(sub).tobytes(), gap)
                 if key not in memo:
                     memo[key] = pins.enumerate_alignments([list(a), list(b), list(c)], sub, gap)[0]
                 best = max(best, memo[key])

@@ -107,7 +107,7 @@ LOCAL_MUTANTS = {
 }
 
 
-def _build_local(tmp_path, name, old, new):
+def _build_local(tmp_path, name, old, new, fn="oracle_score_local"):
     src = open(SRC).read()
     assert src.count(old) == 1, name
     path = tmp_path / f"{name}.c"
@@ -118,15 +118,16 @@ def _build_local(tmp_path, name, old, new):
     lib = ctypes.CDLL(str(so))
     u8p, i32p, i64p = (ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
                        ctypes.POINTER(ctypes.c_int64))
-    lib.oracle_score_local.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, u8p,
-                                       ctypes.c_int64, i32p, ctypes.c_int32, i64p]
+    f = getattr(lib, fn)
+    f.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, u8p, ctypes.c_int64, i32p,
+                  ctypes.c_int32, i64p]
 
     def score(trip, sub, gap):
         arrs = [np.ascontiguousarray(s, np.uint8) for s in trip]
         sub = np.ascontiguousarray(sub, np.int32).reshape(16)
         out = ctypes.c_int64()
-        lib.oracle_score_local(*[x for a in arrs for x in (a.ctypes.data_as(u8p), a.size)],
-                               sub.ctypes.data_as(i32p), gap, ctypes.byref(out))
+        f(*[x for a in arrs for x in (a.ctypes.data_as(u8p), a.size)],
+          sub.ctypes.data_as(i32p), gap, ctypes.byref(out))
         return out.value
 
     return score
@@ -154,3 +155,54 @@ def test_unmodified_local_source_passes(tmp_path):
 def test_local_mutant_is_caught(tmp_path, name):
     old, new = LOCAL_MUTANTS[name]
     assert not _local_pins_pass(_build_local(tmp_path, name, old, new))
+
+
+# Plausible mistakes in the semi-global variant (each must fail its pins).
+SEMI_MUTANTS = {
+    "semi_axes_from_moves": ("if ((i == 0) + (j == 0) + (k == 0) >= 2) {",
+                             "if (i + j + k == 0) {"),
+    "semi_last_slice_i_only": ("if ((i == a || j == b || k == c) && m > answer) answer = m;",
+                               "if (i == a && m > answer) answer = m;"),
+    "semi_whole_tensor": ("if ((i == a || j == b || k == c) && m > answer) answer = m;",
+                          "if (m > answer) answer = m;"),
+    "semi_faces_zero_too": ("if ((i == 0) + (j == 0) + (k == 0) >= 2) {",
+                            "if ((i == 0) + (j == 0) + (k == 0) >= 1) {"),
+    "semi_ik_move_wrong_residue": ("t = older[j * stride + (k - 1)] + gg + pair(sub, x, z);",
+                                   "t = older[j * stride + (k - 1)] + gg + pair(sub, y, z);"),
+    "semi_triple_from_this_slice": (
+        "t = older[(j - 1) * stride + (k - 1)] + pair(sub, y, z) + pair(sub, x, y) + pair(sub, x, z);",
+        "t = newer[(j - 1) * stride + (k - 1)] + pair(sub, y, z) + pair(sub, x, y) + pair(sub, x, z);"),
+}
+
+
+def _semi_pins_pass(score) -> bool:
+    from tests.test_oracle_semiglobal import semi_brute
+    rng = np.random.default_rng(8765)
+    memo = {}
+    for trial in range(40):
+        trip = [rng.integers(0, 4, size=int(n)).astype(np.uint8) for n in rng.integers(0, 4, 3)]
+        sub = oracle.DEFAULT_SUB if trial % 2 else pins.random_symmetric_sub(rng)
+        gap = (-2, -1, 0)[trial % 3]
+        if score(trip, sub, gap) != semi_brute(trip, sub, gap, memo):
+            return False
+    # The two hand-derived cases of tests/test_oracle_semiglobal.py.
+    ac, c = np.array([0, 1], np.uint8), np.array([1], np.uint8)
+    if score([ac, ac, c], oracle.DEFAULT_SUB, -2) != 0:
+        return False
+    ag, at = np.array([0, 2], np.uint8), np.array([0, 3], np.uint8)
+    if score([ag, at, ac], oracle.DEFAULT_SUB, -2) != 0:
+        return False
+    x = rng.integers(0, 4, size=9).astype(np.uint8)
+    return score([x, x, x], oracle.DEFAULT_SUB, -2) == 27
+
+
+def test_unmodified_semiglobal_source_passes(tmp_path):
+    line = "if ((i == a || j == b || k == c) && m > answer) answer = m;"
+    assert _semi_pins_pass(_build_local(tmp_path, "semi_identity", line, line,
+                                        fn="oracle_score_semiglobal"))
+
+
+@pytest.mark.parametrize("name", sorted(SEMI_MUTANTS))
+def test_semiglobal_mutant_is_caught(tmp_path, name):
+    old, new = SEMI_MUTANTS[name]
+    assert not _semi_pins_pass(_build_local(tmp_path, name, old, new, fn="oracle_score_semiglobal"))
