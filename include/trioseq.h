@@ -49,17 +49,34 @@ typedef enum trioseq_status {
   TRIOSEQ_ERR_CLOSED = -9       /* server is shutting down */
 } trioseq_status;
 
+/* Alignment kinds (Section II: the value v of Eq. 1 and the tensor's
+ * initialisation select them).
+ *  GLOBAL:      v = -infinity, M[0][0][0] = 0, axes M[i][0][0] = 2*i*gap (and
+ *               likewise for j, k); the score is M[a][b][c].
+ *  SEMI_GLOBAL: v = -infinity, the three axes are 0; the score is the best
+ *               cell on the last slices (i = a, j = b or k = c).
+ *  LOCAL:       the semi-global initialisation with v = 0 (no cell below 0);
+ *               the score is the best cell of the tensor. */
+typedef enum trioseq_kind {
+  TRIOSEQ_GLOBAL = 0,
+  TRIOSEQ_SEMI_GLOBAL = 1,
+  TRIOSEQ_LOCAL = 2
+} trioseq_kind;
+
 /* Scoring scheme (Section II: sigma and the linear gap value alpha).
  * sub must be symmetric (the sum-of-pairs score treats the three sequences
  * alike). gap is the score of one residue against a gap (normally negative);
  * gap against gap always scores 0. Limits: every sub[x][y] - 2*gap lies in
- * [-127, 127] (the kernels keep these terms as bytes). */
+ * [-127, 127] (the kernels keep these terms as bytes); SEMI_GLOBAL and LOCAL
+ * need gap <= 0. kind is a trioseq_kind; semi-global and local plans support
+ * the default 4 x 4 lane tile at 2 waves per SIMD only. */
 typedef struct trioseq_scoring {
   int32_t sub[4][4];
   int32_t gap;
+  int32_t kind;
 } trioseq_scoring;
 
-/* Fills sub with match on the diagonal and mismatch elsewhere. */
+/* Fills sub with match on the diagonal and mismatch elsewhere; kind = GLOBAL. */
 void trioseq_scoring_simple(trioseq_scoring* s, int32_t match, int32_t mismatch, int32_t gap);
 
 /* One triplet as host ASCII. seq[s] may be NULL only if len[s] == 0. */

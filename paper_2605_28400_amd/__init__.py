@@ -1,4 +1,5 @@
-"""Python binding of libtrioseq (exact global 3-way alignment scores on MI355X).
+"""Python binding of libtrioseq (exact 3-way alignment scores on MI355X: global,
+semi-global and local).
 
 Argument marshalling only: every step of the scoring path runs in the HIP
 library (``libtrioseq.so``, built by ``build.py``). If the library is not
@@ -27,8 +28,13 @@ class TrioseqError(RuntimeError):
         self.message = message
 
 
+# Alignment kinds (values of trioseq_kind).
+GLOBAL, SEMI_GLOBAL, LOCAL = 0, 1, 2
+KINDS = {"global": GLOBAL, "semi-global": SEMI_GLOBAL, "local": LOCAL}
+
+
 class Scoring(ctypes.Structure):
-    _fields_ = [("sub", (ctypes.c_int32 * 4) * 4), ("gap", ctypes.c_int32)]
+    _fields_ = [("sub", (ctypes.c_int32 * 4) * 4), ("gap", ctypes.c_int32), ("kind", ctypes.c_int32)]
 
 
 class Triplet(ctypes.Structure):
@@ -144,8 +150,9 @@ def check(status: int) -> None:
         raise TrioseqError(status, lib().trioseq_last_error().decode(errors="replace"))
 
 
-def scoring(match: int = 1, mismatch: int = -1, gap: int = -2, sub=None) -> Scoring:
-    """Scoring scheme; ``sub`` (4x4) overrides match/mismatch."""
+def scoring(match: int = 1, mismatch: int = -1, gap: int = -2, sub=None, kind=GLOBAL) -> Scoring:
+    """Scoring scheme; ``sub`` (4x4) overrides match/mismatch. ``kind`` is
+    GLOBAL, SEMI_GLOBAL or LOCAL (or its name)."""
     s = Scoring()
     if sub is None:
         lib().trioseq_scoring_simple(ctypes.byref(s), match, mismatch, gap)
@@ -155,6 +162,7 @@ def scoring(match: int = 1, mismatch: int = -1, gap: int = -2, sub=None) -> Scor
             for y in range(4):
                 s.sub[x][y] = int(sub[x][y])
         s.gap = int(gap)
+    s.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
     return s
 
 

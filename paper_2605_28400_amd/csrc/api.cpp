@@ -50,6 +50,12 @@ uint64_t now_ns() {
 
 trioseq_status validate_scoring(const trioseq_scoring* sc) {
   if (!sc) return fail(TRIOSEQ_ERR_INVALID_ARG, "scoring is NULL");
+  if (sc->kind != kGlobal && sc->kind != kSemiGlobal && sc->kind != kLocal)
+    return fail(TRIOSEQ_ERR_INVALID_ARG, "scoring kind must be global, semi-global or local");
+  // The semi-global and local kernels rely on M' = M - 2*gap*(i+j+k) >= 0
+  // for their axis values and floors.
+  if (sc->kind != kGlobal && sc->gap > 0)
+    return fail(TRIOSEQ_ERR_INVALID_ARG, "semi-global and local scoring need gap <= 0");
   for (int x = 0; x < 4; ++x)
     for (int y = 0; y < 4; ++y) {
       if (sc->sub[x][y] != sc->sub[y][x])
@@ -70,6 +76,8 @@ trioseq_status check_range(const trioseq_scoring& sc, uint64_t a, uint64_t b, ui
     for (int y = 0; y < 4; ++y)
       maxterm = std::max<int64_t>(maxterm, (int64_t)sc.sub[x][y] - 2 * (int64_t)sc.gap);
   // Shifted scores lie in [0, d * maxterm]; the true score adds 2*gap*d.
+  // Semi-global axes and local floors put cells at M' = -2*gap*(i+j+k).
+  if (sc.kind != kGlobal) maxterm = std::max<int64_t>(maxterm, -2 * (int64_t)sc.gap);
   const long double hi = (long double)d * (long double)maxterm;
   const long double shift = (long double)d * 2.0L * (long double)sc.gap;
   if (hi >= (long double)(1 << 27) || shift >= (long double)(1 << 30) ||
@@ -93,6 +101,7 @@ DevScoring make_dev_scoring(const trioseq_scoring& sc) {
   for (int r = 0; r < 4; ++r)
     for (int s = 0; s < 4; ++s) d.pair_tab[4 * r + s] = sc.sub[r][s] - 2 * sc.gap;
   d.gap2 = 2 * sc.gap;
+  d.kind = sc.kind;
   return d;
 }
 
@@ -165,7 +174,7 @@ Boundary carve_boundary(const KernelShape& ks, uint32_t max_n0, int* q) {
 SweepArgs make_sweep_args(const uint32_t* words, const TripletDesc* desc, const JobDesc* jobs,
                           uint32_t njobs, uint32_t lds_n0, int32_t* scores, int* counter, int* ctl,
                           int* face, uint64_t face_stride, int* pface, const Boundary& bnd,
-                          const DevScoring& sc) {
+                          int* red, const DevScoring& sc) {
   SweepArgs a;
   a.words = words;
   a.desc = desc;
@@ -182,6 +191,7 @@ SweepArgs make_sweep_args(const uint32_t* words, const TripletDesc* desc, const 
     a.bnd_plain[k] = bnd.plain[k];
     a.bnd_tagged[k] = bnd.tagged[k];
   }
+  a.red = red;
   a.sc = sc;
   return a;
 }
@@ -220,6 +230,8 @@ struct trioseq_plan {
   int* d_pface = nullptr;    // panel-face pool of split triplets
   int* d_bnd = nullptr;      // sentinel faces
   Boundary bnd{};
+  int* d_red = nullptr;      // per-triplet reduction pairs (semi-global, local)
+  uint32_t red_pairs = 0;
   // graph replay
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
@@ -241,6 +253,7 @@ static void plan_free(trioseq_plan* p) {
   (void)hipFree(p->d_face);
   (void)hipFree(p->d_pface);
   (void)hipFree(p->d_bnd);
+  (void)hipFree(p->d_red);
   delete p;
 }
 
@@ -251,6 +264,7 @@ void trioseq_scoring_simple(trioseq_scoring* s, int32_t match, int32_t mismatch,
   for (int x = 0; x < 4; ++x)
     for (int y = 0; y < 4; ++y) s->sub[x][y] = x == y ? match : mismatch;
   s->gap = gap;
+  s->kind = TRIOSEQ_GLOBAL;
 }
 
 const char* trioseq_last_error(void) { return g_err.c_str(); }
@@ -304,7 +318,8 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   if (o.grid < 0) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: negative grid");
   KernelShape ks{o.tile_rows ? o.tile_rows : 4, o.tile_cols ? o.tile_cols : 4,
                  o.waves_per_simd ? o.waves_per_simd : 2};
-  if (!shape_supported(ks)) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: unsupported tile shape");
+  if (!shape_supported(ks, sc.kind))
+    return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: unsupported tile shape for this scoring kind");
   std::vector<uint64_t> offs;
   if (!off) {
     offs.resize(3 * n);
@@ -368,9 +383,10 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   if (!o.waves_per_simd && L->modes == 1 && ks.rj * ks.rk <= 16) {
     KernelShape k4 = ks;
     k4.wpe = 4;
-    if (shape_supported(k4)) ks = k4;
+    if (shape_supported(k4, sc.kind)) ks = k4;
   }
   L->ks = ks;
+  L->kind = sc.kind;
   L->panels = panels;
   L->lds_n0 = max_n0;
   L->cells = cells;
@@ -410,7 +426,7 @@ static int log2_bucket(double v) {
   return b;
 }
 
-std::string length_profile(const uint32_t* lens, size_t n) {
+std::string length_profile(const uint32_t* lens, size_t n, int kind) {
   uint32_t mx = 0;
   double cells = 0;
   for (size_t t = 0; t < n; ++t) {
@@ -418,12 +434,12 @@ std::string length_profile(const uint32_t* lens, size_t n) {
     mx = std::max({mx, l[0], l[1], l[2]});
     cells += (double)l[0] * l[1] * l[2];
   }
-  return std::to_string(log2_bucket((double)n)) + "/" + std::to_string(log2_bucket(mx)) + "/" +
-         std::to_string(log2_bucket(cells));
+  return std::to_string(kind) + "/" + std::to_string(log2_bucket((double)n)) + "/" +
+         std::to_string(log2_bucket(mx)) + "/" + std::to_string(log2_bucket(cells));
 }
 
-void apply_tuned(const uint32_t* lens, size_t n, trioseq_plan_options* o) {
-  const std::string key = length_profile(lens, n);
+void apply_tuned(const uint32_t* lens, size_t n, int kind, trioseq_plan_options* o) {
+  const std::string key = length_profile(lens, n, kind);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (const auto& kv : g_tuned)
     if (kv.first == key) {
@@ -446,7 +462,7 @@ static void remember_tuned(const std::string& key, const trioseq_plan_options& o
 trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested, int* grid,
                            int* waves_per_cu) {
   int w = 0;
-  TRIOSEQ_HIP(sweep_occupancy(L.ks, L.modes, L.lds_n0, &w), "occupancy");
+  TRIOSEQ_HIP(sweep_occupancy(L.ks, L.modes, L.kind, L.lds_n0, &w), "occupancy");
   int g = requested ? requested : dp.cus * std::max(1, w);
   g = (int)std::min<size_t>((size_t)g, std::max<size_t>(L.jobs.size(), 1));
   *grid = g;
@@ -465,7 +481,7 @@ trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_of
   if (!scp) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: scoring is NULL");
   trioseq_plan_options o{-1, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
-  if (!o.tile_rows && !o.tile_cols && !o.waves_per_simd && lens) apply_tuned(lens, n, &o);
+  if (!o.tile_rows && !o.tile_cols && !o.waves_per_simd && lens) apply_tuned(lens, n, scp->kind, &o);
   // Inputs are validated (by the layout) before the device is touched; the
   // layout is redone if the device's size changes the split rule's hint.
   Layout L;
@@ -532,6 +548,10 @@ trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_of
       return hip_bail(e, "hipMalloc panel faces");
     if ((e = hipMemset(p->d_pface, 0, pool_bytes)) != hipSuccess) return hip_bail(e, "hipMemset");
   }
+  p->red_pairs = L.red_pairs();
+  if (p->red_pairs &&
+      (e = hipMalloc((void**)&p->d_red, (uint64_t)p->red_pairs * 2 * sizeof(int))) != hipSuccess)
+    return hip_bail(e, "hipMalloc reduction pairs");
   const uint64_t bnd_ints = boundary_ints(L.ks, L.lds_n0);
   if ((e = hipMalloc((void**)&p->d_bnd, bnd_ints * sizeof(int))) != hipSuccess)
     return hip_bail(e, "hipMalloc boundary");
@@ -539,6 +559,7 @@ trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_of
   if ((e = launch_init_boundary(L.ks, p->bnd, nullptr)) != hipSuccess) return hip_bail(e, "boundary init");
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_bail(e, "boundary init");
   p->workspace_bytes = face_bytes + pool_bytes + bnd_ints * sizeof(int) +
+                       (uint64_t)p->red_pairs * 2 * sizeof(int) +
                        n * sizeof(TripletDesc) + L.jobs.size() * sizeof(JobDesc) + 512;
   if (p->use_graph) {
     if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
@@ -552,10 +573,11 @@ static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t
                                hipStream_t s) {
   if (p->n == 0) return hipSuccess;
   hipError_t e;
-  if ((e = launch_prepare(p->d_ctl, p->d_counter, s)) != hipSuccess) return e;
+  if ((e = launch_prepare(p->d_ctl, p->d_counter, p->d_red, p->red_pairs, s)) != hipSuccess)
+    return e;
   SweepArgs a = make_sweep_args(d_words, p->d_desc, p->d_jobs, p->njobs, p->lds_n0, d_scores,
                                 p->d_counter, p->d_ctl, p->d_face, p->face_stride, p->d_pface,
-                                p->bnd, p->sc);
+                                p->bnd, p->d_red, p->sc);
   return launch_sweep(p->ks, p->modes, a, p->grid, s);
 }
 
@@ -750,7 +772,7 @@ trioseq_status trioseq_autotune(const uint32_t* lens, const uint64_t* word_off, 
   (void)hipFree(d_out);
   if (st != TRIOSEQ_OK) return st;
   if (r.tried == 0) return fail(TRIOSEQ_ERR_DEVICE, "autotune: no configuration could be planned");
-  if (r.best.waves_per_simd) remember_tuned(length_profile(lens, n), r.best);
+  if (r.best.waves_per_simd) remember_tuned(length_profile(lens, n, sc->kind), r.best);
   *out = r;
   return TRIOSEQ_OK;
 }

@@ -52,12 +52,13 @@ Boundary carve_boundary(const KernelShape& ks, uint32_t max_n0, int* base);
 SweepArgs make_sweep_args(const uint32_t* words, const TripletDesc* desc, const JobDesc* jobs,
                           uint32_t njobs, uint32_t lds_n0, int32_t* scores, int* counter, int* ctl,
                           int* face, uint64_t face_stride, int* pface, const Boundary& bnd,
-                          const DevScoring& sc);
+                          int* red, const DevScoring& sc);
 
 // Host-side plan of one batch: validation, per-triplet axis choice, the job
 // queue in dependency order, and the device memory the sweep needs.
 struct Layout {
   KernelShape ks{4, 4, 2};
+  int kind = 0;    // alignment kind of the scoring
   int modes = 1;   // bit 0 whole-triplet jobs, bit 1 panel jobs
   int engine = 0;  // 0 all whole, 1 all split, 2 mixed
   int panels = 0;
@@ -67,6 +68,9 @@ struct Layout {
   std::vector<JobDesc> jobs;
   uint64_t face_stride = 0;  // ints of whole-triplet workspace per wave
   uint64_t pool_ints = 0;    // ints of panel faces of split triplets
+  // Per-triplet reduction pairs the run needs (semi-global and local scoring
+  // of split triplets): 2 * red_pairs ints.
+  uint32_t red_pairs() const { return kind != 0 && (modes & 2) ? (uint32_t)desc.size() : 0u; }
 };
 
 // Validates and lays out n triplets (lens[3t+s], word offsets off[3t+s]).
@@ -77,9 +81,9 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
                             Layout* L);
 // Resident wavefronts per compute unit assumed when sizing the split rule.
 constexpr int kWavesPerCuHint = 8;
-// Autotuning cache keyed by a batch's length profile.
-std::string length_profile(const uint32_t* lens, size_t n);
-void apply_tuned(const uint32_t* lens, size_t n, trioseq_plan_options* o);
+// Autotuning cache keyed by a batch's length profile and scoring kind.
+std::string length_profile(const uint32_t* lens, size_t n, int kind);
+void apply_tuned(const uint32_t* lens, size_t n, int kind, trioseq_plan_options* o);
 
 // Waves to launch for a layout on this device.
 trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested, int* grid,

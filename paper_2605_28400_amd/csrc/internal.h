@@ -41,7 +41,14 @@ struct DevScoring {
   uint32_t byte_tab[5];
   int32_t pair_tab[16];
   int32_t gap2;  // 2*gap, to undo the shift at the end
+  int32_t kind;  // alignment kind: kGlobal, kSemiGlobal or kLocal
 };
+
+// Alignment kinds (paper, Section II: the value of v and the initialisation
+// of the tensor select global, semi-global or local alignment).
+constexpr int kGlobal = 0;
+constexpr int kSemiGlobal = 1;
+constexpr int kLocal = 2;
 
 // One triplet as the kernels see it: the three sequences already assigned
 // to the sweep axis (0), the row axis (1) and the column axis (2).
@@ -83,6 +90,10 @@ struct SweepArgs {
   int* pface;           // panel-face pool of split triplets
   const int* bnd_plain[3];
   const int* bnd_tagged[3];
+  // Semi-global and local scoring of split triplets: per triplet t,
+  // red[2t] = best value over the panels folded in so far, red[2t + 1] =
+  // panels finished (both reset by k_prepare).
+  int* red;
   DevScoring sc;
 };
 
@@ -93,12 +104,17 @@ struct KernelShape {
 
 // Launchers (sweep.hip).
 hipError_t launch_init_boundary(const KernelShape& ks, const Boundary& b, hipStream_t s);
-hipError_t launch_prepare(int* ctl, int* counter, hipStream_t s);
+// Next run generation, error flag and queue head cleared, and nred
+// per-triplet reduction pairs of red reset (red may be null when nred = 0).
+hipError_t launch_prepare(int* ctl, int* counter, int* red, uint32_t nred, hipStream_t s);
 // modes: bit 0 = whole-triplet jobs present, bit 1 = panel jobs present.
+// The kernel variant follows a.sc.kind.
 hipError_t launch_sweep(const KernelShape& ks, int modes, const SweepArgs& a, int grid,
                         hipStream_t s);
-hipError_t sweep_occupancy(const KernelShape& ks, int modes, uint32_t lds_n0, int* waves_per_cu);
-bool shape_supported(const KernelShape& ks);
+hipError_t sweep_occupancy(const KernelShape& ks, int modes, int kind, uint32_t lds_n0,
+                           int* waves_per_cu);
+// Whether kernels of this tile shape exist for this alignment kind.
+bool shape_supported(const KernelShape& ks, int kind);
 
 inline int panel_rows(const KernelShape& ks) { return kGJ * ks.rj; }
 inline int panel_cols(const KernelShape& ks) { return kGK * ks.rk; }

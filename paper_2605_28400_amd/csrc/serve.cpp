@@ -115,7 +115,8 @@ uint64_t align256(uint64_t v) { return (v + 255) / 256 * 256; }
 // the slot's tagged region instead: L.pool_ints * 4 bytes).
 uint64_t arena_need(const Layout& L, uint64_t words, int grid) {
   return align256(words * 4) + align256(L.desc.size() * sizeof(TripletDesc)) +
-         align256(L.jobs.size() * sizeof(JobDesc)) + align256((uint64_t)grid * L.face_stride * 4);
+         align256(L.jobs.size() * sizeof(JobDesc)) + align256((uint64_t)L.red_pairs() * 8) +
+         align256((uint64_t)grid * L.face_stride * 4);
 }
 
 void record_result(trioseq_server* s, const Request& r, int32_t score, int32_t status, uint64_t t) {
@@ -186,6 +187,8 @@ trioseq_status launch_round(trioseq_server* s, Slot& sl, std::vector<Request>& b
   a += align256(n * sizeof(TripletDesc));
   JobDesc* d_jobs = (JobDesc*)a;
   a += align256(L.jobs.size() * sizeof(JobDesc));
+  int* d_red = (int*)a;
+  a += align256((uint64_t)L.red_pairs() * 8);
   int* d_face = (int*)a;
   int* d_pface = sl.tagged;
 
@@ -196,11 +199,11 @@ trioseq_status launch_round(trioseq_server* s, Slot& sl, std::vector<Request>& b
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_jobs, sl.h_jobs, L.jobs.size() * sizeof(JobDesc), hipMemcpyHostToDevice,
                        sl.stream);
-  if (e == hipSuccess) e = launch_prepare(sl.ctl, sl.ctl + 64, sl.stream);
+  if (e == hipSuccess) e = launch_prepare(sl.ctl, sl.ctl + 64, d_red, L.red_pairs(), sl.stream);
   if (e == hipSuccess) {
     SweepArgs args = make_sweep_args(d_words, d_desc, d_jobs, (uint32_t)L.jobs.size(), L.lds_n0,
                                      sl.d_scores, sl.ctl + 64, sl.ctl, d_face, L.face_stride, d_pface,
-                                     s->bnd, s->dsc);
+                                     s->bnd, d_red, s->dsc);
     e = launch_sweep(L.ks, L.modes, args, grid, sl.stream);
   }
   if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);

@@ -1,8 +1,13 @@
-// gfx950 kernels for exact global 3-way alignment scoring.
+// gfx950 kernels for exact 3-way alignment scoring.
 //
-// What is computed (paper, Section II, Eq. 1 with the global initialisation):
-// M[i][j][k] is the best of seven predecessor moves plus the sum-of-pairs
-// score of the move's column, M[0][0][0] = 0, and the answer is M[n0][n1][n2].
+// What is computed (paper, Section II, Eq. 1): M[i][j][k] is the best of seven
+// predecessor moves plus the sum-of-pairs score of the move's column (or v).
+//  * global: v = -infinity, M[0][0][0] = 0, the answer is M[n0][n1][n2];
+//  * semi-global: as global, but the three axes M[i][0][0], M[0][j][0],
+//    M[0][0][k] are 0, and the answer is the best cell on the last slices
+//    i = n0, j = n1 or k = n2;
+//  * local: the semi-global initialisation with v = 0 (no cell below 0), and
+//    the answer is the best cell of the tensor.
 //
 // Shifted recurrence. Every move adds 2*gap per consumed residue on top of
 // its substitution terms, so with M'(i,j,k) = M(i,j,k) - 2*gap*(i+j+k) the
@@ -194,10 +199,24 @@ __device__ __forceinline__ void lds_put(int* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <int MODE, int RJ, int RK>
-__device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring& sc,
-                            const uint32_t* __restrict__ words, const TripletDesc& td, int pj, int pk,
-                            const PanelIO& io, int32_t* score_out, SplitLds<RJ, RK>* split = nullptr) {
+// Global scoring: the lane owning cell (n0, n1, n2) writes the score to
+// score_out (non-null for the triplet's last panel only); returns 0.
+// Semi-global and local scoring: returns this lane's best unshifted value
+// over the panel's cells that the answer ranges over (the caller reduces).
+//
+// In the shifted form the floor v = 0 of local scoring is the per-cell bound
+// M'(i,j,k) >= F(i,j,k) = g*(i+j+k) with g = -2*gap >= 0, and the semi-global
+// axes hold M' = F. Within a lane's tile F depends on the anti-diagonal
+// d = r + c only, so both are handled per diagonal class: F_d = F_0 + g*d.
+// Rows past n1 and columns past n2 (tile padding) use the row/column-0
+// tables, so their cells never exceed the best cell of the tensor (every
+// move into the padding that consumes a padding residue scores -128, and the
+// remaining moves mirror moves inside the tensor at gap <= 0); slices outside
+// 0..n0 are excluded from the best and unfloored before slice 0.
+template <int MODE, int KIND, int RJ, int RK>
+__device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring& sc,
+                           const uint32_t* __restrict__ words, const TripletDesc& td, int pj, int pk,
+                           const PanelIO& io, int32_t* score_out, SplitLds<RJ, RK>* split = nullptr) {
   constexpr bool WIDE = MODE == kTagged;
   constexpr bool SPC = MODE == kSplitCompute;
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
@@ -211,18 +230,19 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
                  bt3 = sc.byte_tab[3], btz = sc.byte_tab[4];
 
   // Row/column tables of this lane's tile.
+  constexpr bool PAD = KIND != kGlobal;  // padding rows/columns use the -128 table
   uint32_t TB[RJ], TC[RK], cco[RK];
 #pragma unroll
   for (int r = 0; r < RJ; ++r) {
     const int j = j0 + r;
     const uint32_t b = (j >= 1 && j <= n1) ? residue_at(words, td.off[1], (uint32_t)(j - 1)) : 0u;
-    TB[r] = j == 0 ? btz : pick4(b, bt0, bt1, bt2, bt3);
+    TB[r] = (j == 0 || (PAD && j > n1)) ? btz : pick4(b, bt0, bt1, bt2, bt3);
   }
 #pragma unroll
   for (int c = 0; c < RK; ++c) {
     const int k = k0 + c;
     cco[c] = (k >= 1 && k <= n2) ? residue_at(words, td.off[2], (uint32_t)(k - 1)) : 0u;
-    TC[c] = k == 0 ? btz : pick4(cco[c], bt0, bt1, bt2, bt3);
+    TC[c] = (k == 0 || (PAD && k > n2)) ? btz : pick4(cco[c], bt0, bt1, bt2, bt3);
   }
   // C = s(b,c) - 2*gap (byte c of b's table, the matrix being symmetric),
   // packed four per register; -128 on row 0 and column 0, where every
@@ -239,7 +259,8 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
       for (int b = 0; b < 4; ++b) {
         const int cc = 4 * w + b;
         if (cc >= RK) break;
-        const int v = (j0 + r == 0 || k0 + cc == 0) ? -128 : sbyte(TB[r], cco[cc] << 3);
+        const bool pad = PAD && (j0 + r > n1 || k0 + cc > n2);
+        const int v = (j0 + r == 0 || k0 + cc == 0 || pad) ? -128 : sbyte(TB[r], cco[cc] << 3);
         packed |= (uint32_t)(v & 0xFF) << (8 * b);
       }
       Cp[r][w] = packed;
@@ -261,7 +282,17 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
 
   // The lane holding cell (n1, n2) of the last panel keeps slice n0.
   const int rsel = n1 - j0, csel = n2 - k0;
-  const bool own = score_out && rsel >= 0 && rsel < RJ && csel >= 0 && csel < RK;
+  const bool own = KIND == kGlobal && score_out && rsel >= 0 && rsel < RJ && csel >= 0 && csel < RK;
+
+  // Semi-global and local scoring. fi = g*(i + j0 + k0) for the lane's slice
+  // i of the current step; best = the lane's best unshifted value so far.
+  constexpr int ND = RJ + RK - 1;  // anti-diagonal classes of a tile
+  const int g2n = -sc.gap2;
+  int fi = g2n * (j0 + k0 - y - x);
+  int best = KIND == kLocal ? 0 : INT32_MIN;
+  // Semi-global: the lane holds row n1 / column n2 (cells past them are padding).
+  const bool has_row = rsel >= 0 && rsel < RJ, has_col = csel >= 0 && csel < RK;
+  const bool axis_panel = pj == 0 || pk == 0;
 
   // Face resources: face_rows(n0) rows cover every staging load and store.
   const uint32_t frows = face_rows((uint32_t)n0);
@@ -501,9 +532,39 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
 #pragma unroll
       for (int r = 0; r < RJ; ++r) Lh[r] = lp[r];
       const int corner = cb[s * c_str];
+      const int i = t - y - x;  // this lane's slice
+
+      if (KIND == kSemiGlobal && axis_panel) {
+        // The axes hold 0 (M' = F): the virtual predecessors across the
+        // tensor edge carry the axis values, which the single move from
+        // there (+0) copies in. Every other move from the virtual row or
+        // column scores -128 through the row/column-0 tables.
+        if (j0 == 0) {
+#pragma unroll
+          for (int cc = 0; cc < RK; ++cc) T[cc] = i == 0 ? g2n * (k0 + cc) : T[cc];
+          if (k0 == 0) T[0] = i >= 0 ? g2n * i : T[0];
+        }
+        if (k0 == 0) {
+#pragma unroll
+          for (int r = 0; r < RJ; ++r) Lh[r] = i == 0 ? g2n * (j0 + r) : Lh[r];
+        }
+      }
+      // Local floors per anti-diagonal class; none before slice 0, whose
+      // previous slice is outside the tensor.
+      int F[ND];
+      if (KIND != kGlobal) {
+        // Keeps the compiler from computing every step's floors of a chunk
+        // up front (they would all stay live in registers).
+        asm volatile("" : "+v"(fi));
+      }
+      if (KIND == kLocal) {
+        const int fb = i >= 0 ? fi : kSent;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) F[d] = fb + g2n * d;
+      }
 
       int N[RJ][RK];
-      if (RJ * RK <= 16) {
+      if (RJ * RK <= 16 && KIND == kGlobal) {
         // Candidates from the previous slice only (the moves that consume
         // S0's residue), computed while the halo reads are in flight: Q = the
         // best of the single move along S0 and its two double moves, X7 the
@@ -517,6 +578,7 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
             const int up_prev = r ? P[r - 1][cc] : Tp[cc];
             const int left_prev = cc ? P[r][cc - 1] : Lp[r];
             Q[r][cc] = max3i(P[r][cc], up_prev + A[r], left_prev + B[cc]);
+            if (KIND == kLocal) Q[r][cc] = max(Q[r][cc], F[r + cc]);
             X7[r][cc] = D[r][cc] + A[r] + B[cc];
           }
         }
@@ -547,10 +609,47 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
             const int x6 = diag_cur + (int)(int8_t)(uint8_t)(Cp[r][cc >> 2] >> (8 * (cc & 3)));
             const int x7 = D[r][cc] + A[r] + B[cc];
             N[r][cc] = max3i(max3i(P[r][cc], up_cur, left_cur), max3i(x4, x5, x6), x7);
+            if (KIND == kLocal) N[r][cc] = max(N[r][cc], F[r + cc]);
             D[r][cc] = x6;
           }
         }
       }
+
+      if (KIND == kLocal) {
+        // Best class maximum minus its floor F_d = fi + g*d, counted on
+        // slices 0..n0. The per-class offsets g*d are wave-uniform, so only
+        // fi stays live past the cell loop.
+        int sb = INT32_MIN;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          int m = INT32_MIN;
+#pragma unroll
+          for (int r = 0; r < RJ; ++r)
+            if (d - r >= 0 && d - r < RK) m = max(m, N[r][d - r]);
+          sb = max(sb, m - g2n * d);
+        }
+        best = max(best, (uint32_t)i <= (uint32_t)n0 ? sb - fi : 0);
+      } else if (KIND == kSemiGlobal) {
+        // Cells of the last slices, on slices 0..n0: all of slice n0, row n1
+        // and column n2. Padding cells never exceed the best of these, so
+        // they need no mask; the others get kSent added.
+        if ((uint32_t)i <= (uint32_t)n0 && (i == n0 || has_row || has_col)) {
+          const int all = i == n0 ? 0 : kSent;
+          int cpen[RK];
+#pragma unroll
+          for (int cc = 0; cc < RK; ++cc) cpen[cc] = max(all, cc == csel ? 0 : kSent);
+          int sb = INT32_MIN;
+#pragma unroll
+          for (int r = 0; r < RJ; ++r) {
+            const int rp = r == rsel ? 0 : kSent;
+#pragma unroll
+            for (int cc = 0; cc < RK; ++cc)
+              sb = max(sb, N[r][cc] + max(rp, cpen[cc]) - g2n * (r + cc));
+          }
+          best = max(best, sb - fi);
+        }
+      }
+      fi += g2n;
 
 #pragma unroll
       for (int r = 0; r < RJ; ++r) L.sR[lane][r] = N[r][RK - 1];
@@ -632,12 +731,42 @@ __device__ void sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring
   if (own)
     __hip_atomic_store(score_out, L.cap[rsel * RK + csel] + sc.gap2 * (n0 + n1 + n2),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  return KIND == kGlobal ? 0 : best;
 }
 
-__device__ __forceinline__ int wave_min(int v) {
+__device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, 64));
+  for (int m = 32; m >= 1; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
   return v;
+}
+
+// Semi-global and local scoring, whole-triplet job: the wave's best over all
+// panels is the score.
+__device__ __forceinline__ void finish_whole(int32_t* score_out, int best) {
+  const int wb = wave_max(best);
+  if ((threadIdx.x & 63) == 0) __hip_atomic_store(score_out, wb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Semi-global and local scoring, panel job of a split triplet: the panel's
+// best is folded into the triplet's accumulator, then the panel counts
+// itself finished. The release of that count orders the fold before it, so
+// the panel that finishes last (its count acquires every earlier one) reads
+// the final best and writes the score, or INT32_MIN if a wait of the run gave
+// up.
+__device__ __forceinline__ void finish_panel(const SweepArgs& a, uint32_t trip, uint32_t out,
+                                             int npanels, int best) {
+  const int wb = wave_max(best);
+  if ((threadIdx.x & 63) == 0) {
+    int* acc = a.red + 2 * (uint64_t)trip;
+    __hip_atomic_fetch_max(acc, wb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int prev = __hip_atomic_fetch_add(acc + 1, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == npanels - 1) {
+      const int v = __hip_atomic_load(acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const bool bad = __hip_atomic_load(a.ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+      __hip_atomic_store(a.scores + out, bad ? INT32_MIN : v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
 }
 
 // The memory wave of a two-wave panel workgroup. It keeps the compute wave's
@@ -803,7 +932,7 @@ __device__ void panel_memory(SplitLds<RJ, RK>& S, const TripletDesc& td, const P
 // moves faces (panel_memory). The workgroup pops jobs from the same queue
 // and in the same dependency order as k_sweep, so the same residency
 // argument holds: every producer was popped earlier by a running workgroup.
-template <int RJ, int RK, int WPE>
+template <int RJ, int RK, int WPE, int KIND>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE))) k_panel(SweepArgs a) {
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
   __shared__ SplitLds<RJ, RK> S;
@@ -844,15 +973,19 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
     io.right = pk + 1 < PK ? base + fb_ints : nullptr;
     io.gen = gen;
     io.err = a.ctl + 1;
-    int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
+    int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
+    int best = 0;
     if (wave == 0)
-      sweep_panel<kSplitCompute, RJ, RK>(S.L, shb, a.sc, a.words, td, pj, pk, io, so, &S);
+      best = sweep_panel<kSplitCompute, KIND, RJ, RK>(S.L, shb, a.sc, a.words, td, pj, pk, io, so, &S);
     else
       panel_memory<RJ, RK>(S, td, io);
     __syncthreads();
-    if (so && threadIdx.x == 0 &&
-        __hip_atomic_load(io.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+    if (KIND != kGlobal) {
+      if (wave == 0) finish_panel(a, jd.trip, td.out, PJ * PK, best);
+    } else if (so && threadIdx.x == 0 &&
+               __hip_atomic_load(io.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
       __hip_atomic_store(so, INT32_MIN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
@@ -867,7 +1000,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
 //    waves of the grid are resident.
 // MODES: bit 0 = the plan has whole-triplet jobs, bit 1 = panel jobs; a
 // kernel built for one kind only carries no registers for the other.
-template <int RJ, int RK, int WPE, int MODES>
+template <int RJ, int RK, int WPE, int MODES, int KIND>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) k_sweep(SweepArgs a) {
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
   __shared__ Lds<RJ, RK> L;
@@ -894,6 +1027,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       // Bottom faces, one per panel column ([PK][rows][W]), then the right face.
       int* fb = face;
       int* fr = face + rows * (uint64_t)(PK * W);
+      int best = KIND == kLocal ? 0 : INT32_MIN;
       for (int pj = 0; pj < PJ; ++pj) {
         for (int pk = 0; pk < PK; ++pk) {
           int* col = fb + (uint64_t)pk * rows * W;
@@ -904,10 +1038,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
           io.right = pk + 1 < PK ? fr : nullptr;
           io.gen = 0;
           io.err = nullptr;
-          int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
-          sweep_panel<kPlain, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk, io, so);
+          int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
+          best = max(best, sweep_panel<kPlain, KIND, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk, io, so));
         }
       }
+      if (KIND != kGlobal) finish_whole(a.scores + td.out, best);
     } else if (MODES & 2) {
       const uint32_t p = jd.panel;
       const int pj = (int)(p / (uint32_t)PK), pk = (int)(p % (uint32_t)PK);
@@ -922,10 +1057,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       io.right = pk + 1 < PK ? base + fb_ints : nullptr;
       io.gen = gen;
       io.err = a.ctl + 1;
-      int32_t* so = (pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
-      sweep_panel<kTagged, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk, io, so);
-      if (so && threadIdx.x == 0 &&
-          __hip_atomic_load(io.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+      int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
+      const int best = sweep_panel<kTagged, KIND, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk, io, so);
+      if (KIND != kGlobal)
+        finish_panel(a, jd.trip, td.out, PJ * PK, best);
+      else if (so && threadIdx.x == 0 &&
+               __hip_atomic_load(io.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
         __hip_atomic_store(so, INT32_MIN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
@@ -956,22 +1093,29 @@ __global__ void k_init_boundary(Boundary b, int top_entries, int left_entries, i
   }
 }
 
-// Before each run: next generation, error flag cleared, queue head zeroed.
-__global__ void k_prepare(int* ctl, int* counter) {
+// Before each run: next generation, error flag cleared, queue head zeroed,
+// and the per-triplet reduction pairs reset (best = INT32_MIN, 0 finished).
+__global__ void k_prepare(int* ctl, int* counter, int* red, uint32_t nred) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctl[0] = ctl[0] + 1;
     ctl[1] = 0;
     counter[0] = 0;
   }
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nred; q += gridDim.x * blockDim.x) {
+    red[2 * (uint64_t)q] = INT32_MIN;
+    red[2 * (uint64_t)q + 1] = 0;
+  }
 }
 
-#define TRIOSEQ_SHAPES(X) X(4, 4, 4) X(4, 4, 2) X(8, 4, 2) X(4, 8, 2)
-#define TRIOSEQ_MODES(X, r, c, w) X(r, c, w, 1) X(r, c, w, 2) X(r, c, w, 3)
+// Kernel variants: tile shape (rows, columns, waves per SIMD) and kind.
+#define TRIOSEQ_SHAPES(X) \
+  X(4, 4, 4, 0) X(4, 4, 2, 0) X(8, 4, 2, 0) X(4, 8, 2, 0) X(4, 4, 2, 1) X(4, 4, 2, 2)
+#define TRIOSEQ_MODES(X, r, c, w, k) X(r, c, w, 1, k) X(r, c, w, 2, k) X(r, c, w, 3, k)
 
 }  // namespace
 
-bool shape_supported(const KernelShape& ks) {
-#define X(a, b, w) if (ks.rj == a && ks.rk == b && ks.wpe == w) return true;
+bool shape_supported(const KernelShape& ks, int kind) {
+#define X(a, b, w, k) if (ks.rj == a && ks.rk == b && ks.wpe == w && kind == k) return true;
   TRIOSEQ_SHAPES(X)
 #undef X
   return false;
@@ -986,37 +1130,40 @@ hipError_t launch_init_boundary(const KernelShape& ks, const Boundary& b, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_prepare(int* ctl, int* counter, hipStream_t s) {
-  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(64), 0, s, ctl, counter);
+hipError_t launch_prepare(int* ctl, int* counter, int* red, uint32_t nred, hipStream_t s) {
+  const uint32_t blocks = nred == 0 ? 1 : nred > 256 * 256 ? 256 : (nred + 255) / 256;
+  hipLaunchKernelGGL(k_prepare, dim3(blocks), dim3(256), 0, s, ctl, counter, red, nred);
   return hipGetLastError();
 }
 
 hipError_t launch_sweep(const KernelShape& ks, int modes, const SweepArgs& a, int grid,
                         hipStream_t s) {
   const size_t lds = shift_lds_bytes(a.lds_n0);
-#define Y(r, c, w, m)                                                                  \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m) {                         \
+  const int kind = a.sc.kind;
+#define Y(r, c, w, m, k)                                                               \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m && kind == k) {            \
     if (m == 2)                                                                        \
-      hipLaunchKernelGGL((k_panel<r, c, w>), dim3(grid), dim3(128), lds, s, a);        \
+      hipLaunchKernelGGL((k_panel<r, c, w, k>), dim3(grid), dim3(128), lds, s, a);     \
     else                                                                               \
-      hipLaunchKernelGGL((k_sweep<r, c, w, m>), dim3(grid), dim3(64), lds, s, a);      \
+      hipLaunchKernelGGL((k_sweep<r, c, w, m, k>), dim3(grid), dim3(64), lds, s, a);   \
     return hipGetLastError();                                                          \
   }
-#define X(r, c, w) TRIOSEQ_MODES(Y, r, c, w)
+#define X(r, c, w, k) TRIOSEQ_MODES(Y, r, c, w, k)
   TRIOSEQ_SHAPES(X)
 #undef X
 #undef Y
   return hipErrorInvalidValue;
 }
 
-hipError_t sweep_occupancy(const KernelShape& ks, int modes, uint32_t lds_n0, int* waves_per_cu) {
-#define Y(r, c, w, m)                                                                          \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m)                                   \
-    return m == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_panel<r, c, w>, \
-                                                                 128, shift_lds_bytes(lds_n0))   \
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_sweep<r, c, w, m>, \
-                                                                 64, shift_lds_bytes(lds_n0));
-#define X(r, c, w) TRIOSEQ_MODES(Y, r, c, w)
+hipError_t sweep_occupancy(const KernelShape& ks, int modes, int kind, uint32_t lds_n0,
+                           int* waves_per_cu) {
+#define Y(r, c, w, m, k)                                                                          \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m && kind == k)                         \
+    return m == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_panel<r, c, w, k>, \
+                                                                 128, shift_lds_bytes(lds_n0))      \
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                 \
+                        waves_per_cu, k_sweep<r, c, w, m, k>, 64, shift_lds_bytes(lds_n0));
+#define X(r, c, w, k) TRIOSEQ_MODES(Y, r, c, w, k)
   TRIOSEQ_SHAPES(X)
 #undef X
 #undef Y

@@ -113,3 +113,24 @@ def test_bad_plan_options_rejected():
         assert L.trioseq_plan_create(lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), None, 1,
                                      ctypes.byref(ts.scoring()), ctypes.byref(opts),
                                      ctypes.byref(h)) == -1
+
+
+def test_bad_kinds_rejected():
+    # Validation happens before any device work.
+    L = ts.lib()
+    assert _status(lambda: ts.score(("A", "C", "G"), ts.scoring(kind=3))) == -1
+    assert _status(lambda: ts.score(("A", "C", "G"), ts.scoring(kind=-1))) == -1
+    # Semi-global and local scoring need gap <= 0.
+    for kind in (ts.SEMI_GLOBAL, ts.LOCAL):
+        assert _status(lambda: ts.score(("A", "C", "G"), ts.scoring(2, -1, gap=1, kind=kind))) == -1
+    # ... and the default 4 x 4 tile at two waves per SIMD.
+    lens = np.array([3, 3, 3], dtype=np.uint32)
+    h = ctypes.c_void_p()
+    for kind in (ts.SEMI_GLOBAL, ts.LOCAL):
+        for opts in [ts.PlanOptions(-1, 8, 4, 0, 0, 2), ts.PlanOptions(-1, 4, 8, 0, 0, 2),
+                     ts.PlanOptions(-1, 4, 4, 0, 0, 4)]:
+            assert L.trioseq_plan_create(lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), None,
+                                         1, ctypes.byref(ts.scoring(kind=kind)), ctypes.byref(opts),
+                                         ctypes.byref(h)) == -1
+    assert ts.KINDS == {"global": 0, "semi-global": 1, "local": 2}
+    assert ts.scoring(kind="local").kind == ts.LOCAL

@@ -1,0 +1,184 @@
+"""GPU parity of the semi-global and local kinds (paper, Section II) against the
+CPU oracle, through the C ABI.
+
+Scores are integers, so the bar is equality. Each case runs both kinds on the
+same seeded inputs: whole-triplet jobs (one wavefront per triplet), split
+triplets (panel jobs whose bests are folded across wavefronts), mixed
+batches, few wavefronts, repeated runs and graph replays of one plan (the
+per-run reset of the fold), random scoring schemes, the degenerate shapes, and
+the full-size workloads in the launch configuration the benchmark times.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_28400_amd as ts
+from paper_2605_28400_amd import synth
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+KINDS = [("semi-global", ts.SEMI_GLOBAL, oracle.SEMI_GLOBAL), ("local", ts.LOCAL, oracle.LOCAL)]
+KIND_IDS = [k[0] for k in KINDS]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def run_plan(torch, trips, sc, engine=-1, use_graph=False, reps=1, grid=0):
+    lens, off, words = ts.pack_batch(trips)
+    plan = ts.Plan(lens, off, sc=sc, engine=engine, use_graph=use_graph, grid=grid)
+    d_words = torch.from_numpy(words.view(np.int32)).cuda()
+    outs = []
+    for _ in range(reps):
+        d_scores = torch.full((max(len(trips), 1),), -7, dtype=torch.int32, device="cuda")
+        plan.run(d_words, d_scores)
+        torch.cuda.synchronize()
+        outs.append(d_scores.cpu().numpy()[:len(trips)].copy())
+    info = plan.info()
+    plan.close()
+    return (outs if reps > 1 else outs[0]), info
+
+
+def want_of(trips, okind, sub=oracle.DEFAULT_SUB, gap=oracle.DEFAULT_GAP):
+    return np.asarray(oracle.score_batch(trips, sub, gap, kind=okind), dtype=np.int64)
+
+
+def related(rng, count, lo, hi):
+    """Mutated-ancestor triplets (large local and semi-global scores)."""
+    return [synth.mutated_triplet(rng, int(rng.integers(lo, hi + 1)), float(rng.uniform(0.02, 0.3)))
+            for _ in range(count)]
+
+
+def report(trips, got, want):
+    bad = np.flatnonzero(got != want)
+    return [(int(q), [s.size for s in trips[q]], int(got[q]), int(want[q])) for q in bad[:5]]
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_single_small_fuzz(torch_cuda, name, kind, okind):
+    trips = synth.fuzz(seed=41, count=30, max_len=12)
+    want = want_of(trips, okind)
+    sc = ts.scoring(kind=kind)
+    for q, t in enumerate(trips):
+        say(f"{name} single fuzz #{q} lens={[s.size for s in t]}")
+        assert ts.score(t, sc) == want[q], (q, [s.size for s in t])
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_batch_whole_triplets(torch_cuda, name, kind, okind):
+    rng = np.random.default_rng(42)
+    trips = synth.fuzz(seed=42, count=60, max_len=90) + related(rng, 60, 1, 120)
+    want = want_of(trips, okind)
+    say(f"{name} batch whole n={len(trips)}")
+    got, info = run_plan(torch_cuda, trips, ts.scoring(kind=kind), engine=0)
+    assert info["engine"] == 0
+    assert (got == want).all(), report(trips, got, want)
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_split_triplets(torch_cuda, name, kind, okind):
+    rng = np.random.default_rng(43)
+    shapes = [(150, 90, 201), (64, 64, 64), (1, 130, 77), (97, 1, 160), (0, 70, 140),
+              (200, 33, 0), (129, 129, 129), (33, 257, 65), (65, 65, 300)]
+    sc = ts.scoring(kind=kind)
+    for q, n in enumerate(shapes):
+        if q % 2:
+            anc = synth.uniform_seq(rng, max(n))
+            t = tuple(synth.fix_length(rng, synth.mutate(rng, anc, 0.1), m) for m in n)
+        else:
+            t = tuple(synth.uniform_seq(rng, m) for m in n)
+        want = oracle.score(t, kind=okind)
+        say(f"{name} split lens={n}")
+        got, info = run_plan(torch_cuda, [t], sc, engine=1)
+        assert info["engine"] == (1 if info["panels"] > 0 else 0)
+        assert int(got[0]) == want, (n, int(got[0]), want, info)
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_mixed_batch_and_few_wavefronts(torch_cuda, name, kind, okind):
+    # One large triplet is split (its panels fold their bests), the rest are
+    # swept whole, in one launch; then the same with fewer wavefronts than
+    # panel jobs.
+    rng = np.random.default_rng(44)
+    trips = related(rng, 1, 220, 220) + related(rng, 40, 5, 60)
+    want = want_of(trips, okind)
+    sc = ts.scoring(kind=kind)
+    say(f"{name} mixed batch")
+    got, info = run_plan(torch_cuda, trips, sc)
+    assert info["engine"] == 2, info
+    assert (got == want).all(), report(trips, got, want)
+    for grid in (1, 3, 7):
+        say(f"{name} split grid={grid}")
+        got, info = run_plan(torch_cuda, trips[:1], sc, engine=1, grid=grid)
+        assert info["grid"] == grid
+        assert int(got[0]) == want[0]
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_repeated_runs_and_graph_replays(torch_cuda, name, kind, okind):
+    # The per-triplet folds are reset before every run, eager or replayed.
+    rng = np.random.default_rng(45)
+    trips = related(rng, 2, 150, 190) + related(rng, 10, 10, 50)
+    want = want_of(trips, okind)
+    sc = ts.scoring(kind=kind)
+    for use_graph in (False, True):
+        say(f"{name} repeated runs graph={use_graph}")
+        outs, _ = run_plan(torch_cuda, trips, sc, engine=1, use_graph=use_graph, reps=4)
+        for got in outs:
+            assert (got == want).all(), report(trips, got, want)
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_random_scoring_schemes(torch_cuda, name, kind, okind):
+    rng = np.random.default_rng(46)
+    for trial in range(5):
+        sub = pins.random_symmetric_sub(rng, -4, 5)
+        gap = int(rng.integers(-5, 1))
+        sc = ts.scoring(sub=sub, gap=gap, kind=kind)
+        trips = related(rng, 20, 0, 80) + [tuple(synth.uniform_seq(rng, int(m))
+                                                 for m in rng.integers(0, 80, 3)) for _ in range(10)]
+        want = want_of(trips, okind, sub, gap)
+        say(f"{name} scoring trial {trial} gap={gap}")
+        got, _ = run_plan(torch_cuda, trips, sc, engine=0)
+        assert (got == want).all(), report(trips, got, want)
+        got1, _ = run_plan(torch_cuda, trips[:1], sc, engine=1)
+        assert int(got1[0]) == want[0]
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_single_1k(torch_cuda, name, kind, okind):
+    # Full size: 1024 x 1000 x 1048, split over the whole device (the
+    # configuration the benchmark times); the oracle takes a few seconds.
+    wl = synth.single_1k()
+    t = wl.triplets[0]
+    want = oracle.score(t, kind=okind)
+    say(f"{name} single_1k")
+    got, info = run_plan(torch_cuda, [t], ts.scoring(kind=kind))
+    assert info["engine"] == 1
+    assert int(got[0]) == want
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_batch_8192_sampled(torch_cuda, name, kind, okind):
+    # Full size: all 8192 triplets in one launch; a seeded sample of them is
+    # recomputed by the oracle.
+    wl = synth.batch_8192()
+    rng = np.random.default_rng(47)
+    idx = np.sort(rng.choice(len(wl.triplets), size=48, replace=False))
+    want = want_of([wl.triplets[q] for q in idx], okind)
+    say(f"{name} batch_8192")
+    got, _ = run_plan(torch_cuda, wl.triplets, ts.scoring(kind=kind))
+    assert (got[idx] == want).all(), [(int(q), int(got[q]), int(w)) for q, w in zip(idx, want)
+                                      if got[q] != w][:5]
