@@ -1,6 +1,7 @@
-"""Throughput benchmark of exact global 3-way alignment scoring on one MI355X.
+"""Throughput benchmark of exact 3-way alignment scoring on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--kind global|semi-global|local]
 
 A step is one scoring pass of the whole hot path over the workload's batch,
 with the packed residues already resident in HBM. The default workload is the
@@ -25,8 +26,11 @@ sys.path.insert(0, ROOT)
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 int32 lane-ops/s.
 PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic VALU work per cell: 4 adds + 3 three-input maxima (the shifted
-# recurrence of Eq. 1 with hoisted substitution terms).
-OPS_PER_CELL = 7
+# recurrence of Eq. 1 with hoisted substitution terms). Local scoring adds the
+# floor v = 0 and the running maximum over the tensor (one maximum each);
+# semi-global adds maxima over the last slices only (O(n^2) cells).
+OPS_PER_CELL_OF = {"global": 7, "semi-global": 7, "local": 9}
+OPS_PER_CELL = OPS_PER_CELL_OF["global"]
 
 WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served")
 
@@ -58,6 +62,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single_1k", choices=WORKLOADS)
+    ap.add_argument("--kind", default="global", choices=tuple(OPS_PER_CELL_OF),
+                    help="alignment kind (paper, Section II)")
     ap.add_argument("--tile", default="0x0", help="lane tile RJxRK (0x0 = library default)")
     ap.add_argument("--engine", type=int, default=-1)
     ap.add_argument("--graph", type=int, default=1)
@@ -74,9 +80,10 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(workload, budget_s: float = 20.0):
+def cpu_baseline(workload, budget_s: float = 20.0, kind: str = "global"):
     """The oracle, as is, on a bounded sample of the workload (host cores)."""
     import oracle
+    okind = {"global": oracle.GLOBAL, "semi-global": oracle.SEMI_GLOBAL, "local": oracle.LOCAL}[kind]
     from paper_2605_28400_amd import synth
     trips = workload.triplets
     cores = 1 if len(trips) == 1 else (os.cpu_count() or 1)
@@ -92,7 +99,7 @@ def cpu_baseline(workload, budget_s: float = 20.0):
             sample = "the whole triplet (1 thread)"
         cells = synth.cells(t)
         t0 = time.perf_counter()
-        score = oracle.score(t)
+        score = oracle.score(t, kind=okind)
         dt = time.perf_counter() - t0
         return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": cores, "kind": "oracle",
                 "sample": sample, "seconds": round(dt, 3)}, score
@@ -100,7 +107,7 @@ def cpu_baseline(workload, budget_s: float = 20.0):
     # at the oracle's measured rate, on all host cores.
     probe = trips[:cores]
     t0 = time.perf_counter()
-    oracle.score_batch(probe, threads=cores)
+    oracle.score_batch(probe, threads=cores, kind=okind)
     rate = sum(synth.cells(t) for t in probe) / max(time.perf_counter() - t0, 1e-6)
     take, acc = 0, 0.0
     for t in trips:
@@ -111,14 +118,15 @@ def cpu_baseline(workload, budget_s: float = 20.0):
     sample = trips[:take]
     cells = sum(synth.cells(t) for t in sample)
     t0 = time.perf_counter()
-    oracle.score_batch(sample, threads=cores)
+    oracle.score_batch(sample, threads=cores, kind=okind)
     dt = time.perf_counter() - t0
     return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": cores, "kind": "oracle",
             "sample": f"first {take} of {len(trips)} triplets on {cores} threads",
             "seconds": round(dt, 3)}, None
 
 
-def per_triplet(ts, torch, trips, sample: int, stream, ref_scores=None, spread: bool = False):
+def per_triplet(ts, torch, trips, sample: int, stream, ref_scores=None, spread: bool = False,
+                sc=None):
     """The plain per-triplet path on the same GPU: one plan per triplet
     (inputs resident in HBM), built and warmed untimed, then one timed,
     synchronised run each; plans are freed one by one, so large triplets
@@ -131,7 +139,7 @@ def per_triplet(ts, torch, trips, sample: int, stream, ref_scores=None, spread: 
     for q in idx:
         t = trips[int(q)]
         lens, off, words = ts.pack_batch([t])
-        plan = ts.Plan(lens, off)
+        plan = ts.Plan(lens, off, sc=sc)
         w = torch.from_numpy(words.view(np.int32)).cuda()
         sc = torch.zeros(1, dtype=torch.int32, device="cuda")
         plan.run(w, sc, stream)
@@ -164,6 +172,8 @@ def served(args):
     import torch
     import paper_2605_28400_amd as ts
     from paper_2605_28400_amd import synth
+    sc = ts.scoring(kind=args.kind)
+    ops = OPS_PER_CELL_OF[args.kind]
     print(f"generating {args.requests} requests", file=sys.stderr, flush=True)
     workload, gaps = synth.served_stream(count=args.requests)
     trips = workload.triplets
@@ -173,7 +183,7 @@ def served(args):
     budget = 64 << 30
     # Closed-loop capacity on the first requests.
     calib = min(len(trips), max(200, len(trips) // 50))
-    srv = ts.Server(max_len=max_len, max_device_bytes=budget)
+    srv = ts.Server(max_len=max_len, sc=sc, max_device_bytes=budget)
     t0 = time.perf_counter()
     cids = [srv.submit(t) for t in trips[:calib]]
     for rid in cids:
@@ -182,7 +192,7 @@ def served(args):
     srv.close()
     rate = args.load * cap / cells_each.mean()
     print(f"capacity {cap / 1e9:.1f} GCUPS -> offered {rate:.1f} requests/s", file=sys.stderr, flush=True)
-    srv = ts.Server(max_len=max_len, max_device_bytes=budget)
+    srv = ts.Server(max_len=max_len, sc=sc, max_device_bytes=budget)
     arrivals = np.cumsum(gaps / rate)
     ids = []
     start = time.perf_counter()
@@ -206,7 +216,8 @@ def served(args):
     ok = all(r["status"] == 0 for r in res.values())
     served_scores = np.array([res[rid]["score"] for rid in ids])
     stream = torch.cuda.current_stream()
-    alone = per_triplet(ts, torch, trips, args.per_triplet_sample, stream, served_scores, spread=True)
+    alone = per_triplet(ts, torch, trips, args.per_triplet_sample, stream, served_scores, spread=True,
+                        sc=sc)
     rec = {
         "metric": "GCUPS", "value": round(cells / served_s / 1e9, 3), "unit": "GCUPS", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": round(served_s * 1e3, 3), "higher_is_better": True,
@@ -214,13 +225,13 @@ def served(args):
         "config": {"workload": workload.name, "requests": len(trips), "cells": int(cells),
                    "seed": workload.seed, "arrivals": "Poisson", "rate_req_per_s": round(rate, 1),
                    "offered_load": args.load, "closed_loop_capacity_gcups": round(cap / 1e9, 3),
-                   "parallelism": "single GPU"},
+                   "kind": args.kind, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(st["p50_ns"] / 1e6, 3), "p99": round(st["p99_ns"] / 1e6, 3)},
         "rounds": st["rounds"], "all_ok": ok, "per_triplet_path": alone,
-        "roofline": {"bound": "alu", "achieved": round(cells * OPS_PER_CELL / served_s / 1e12, 3),
+        "roofline": {"bound": "alu", "achieved": round(cells * ops / served_s / 1e12, 3),
                      "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOP/s",
-                     "frac": round(cells * OPS_PER_CELL / served_s / 1e12 / PEAK_INT32_TOPS, 4),
-                     "traffic": None, "ops_per_cell": OPS_PER_CELL,
+                     "frac": round(cells * ops / served_s / 1e12 / PEAK_INT32_TOPS, 4),
+                     "traffic": None, "ops_per_cell": ops,
                      "kernel": "k_sweep rounds (continuous batching), wall clock"},
     }
     print(json.dumps(rec), flush=True)
@@ -264,6 +275,8 @@ def main():
     torch.cuda.set_device(0)
     workload = synth.WORKLOADS[args.workload]()
     trips = workload.triplets
+    sc = ts.scoring(kind=args.kind)
+    ops = OPS_PER_CELL_OF[args.kind]
     lens, off, words = ts.pack_batch(trips)
     rj, rk = (int(v) for v in args.tile.split("x"))
     d_words = torch.from_numpy(words.view(np.int32)).cuda()
@@ -271,8 +284,8 @@ def main():
     if len(trips) > 1 and args.autotune and (rj, rk) == (0, 0) and args.engine == -1:
         # Untimed: every configuration is timed on this batch and the fastest
         # one whose scores equal the reference configuration's is kept.
-        tuned = ts.autotune(lens, off, d_words, reps=2)
-    plan = ts.Plan(lens, off, engine=args.engine, tile=(rj, rk), use_graph=bool(args.graph))
+        tuned = ts.autotune(lens, off, d_words, sc=sc, reps=2)
+    plan = ts.Plan(lens, off, sc=sc, engine=args.engine, tile=(rj, rk), use_graph=bool(args.graph))
     info = plan.info()
     d_scores = torch.zeros(len(trips), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -296,7 +309,7 @@ def main():
     cells = float(workload.total_cells)
     ms_per_step = wall * 1e3 / args.steps
     gcups = cells / (ms_per_step * 1e-3) / 1e9
-    achieved = cells * OPS_PER_CELL / (ms_events * 1e-3) / 1e12
+    achieved = cells * ops / (ms_events * 1e-3) / 1e12
     scores = d_scores.cpu().numpy()
 
     rec = {
@@ -306,22 +319,23 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload.name, "triplets": len(trips), "cells": int(cells),
                    "seed": workload.seed, "scoring": "match +1, mismatch -1, gap -2",
+                   "kind": args.kind,
                    "engine": ["whole-triplet", "split", "mixed"][info["engine"]],
                    "tile": f"{info['tile_rows']}x{info['tile_cols']}", "grid": info["grid"],
                    "hip_graph": bool(args.graph), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOP/s",
                      "frac": round(achieved / PEAK_INT32_TOPS, 4),
-                     "traffic": measured_traffic(workload.name),
-                     "kernel_ms": round(ms_events, 4), "ops_per_cell": OPS_PER_CELL,
+                     "traffic": measured_traffic(workload.name) if args.kind == "global" else None,
+                     "kernel_ms": round(ms_events, 4), "ops_per_cell": ops,
                      "kernel": ["k_sweep (persistent job queue, whole-triplet jobs)",
                                 "k_panel (persistent job queue, two-wave panel workgroups)",
                                 "k_sweep (persistent job queue, whole-triplet and panel jobs)"][info["engine"]]},
     }
     # End to end through the host API: pack, upload, lay out, sweep, download.
-    ts.score_batch(trips[:1])
+    ts.score_batch(trips[:1], sc)
     t0 = time.perf_counter()
-    e2e_scores = ts.score_batch(trips)
+    e2e_scores = ts.score_batch(trips, sc)
     e2e_s = time.perf_counter() - t0
     rec["end_to_end"] = {"value": round(cells / e2e_s / 1e9, 3), "unit": "GCUPS",
                          "ms": round(e2e_s * 1e3, 3), "call": "trioseq_score_batch (host triplets)",
@@ -333,9 +347,9 @@ def main():
                                       "tried": tuned["tried"], "rejected": tuned["rejected"]}
     if len(trips) > 1 and args.per_triplet_sample > 0:
         rec["per_triplet_path"] = per_triplet(ts, torch, trips, args.per_triplet_sample, stream,
-                                              scores)
+                                              scores, sc=sc)
     if not args.no_cpu_baseline:
-        cb, oracle_score = cpu_baseline(workload)
+        cb, oracle_score = cpu_baseline(workload, kind=args.kind)
         rec["cpu_baseline"] = cb
         if oracle_score is not None and len(trips) == 1 and cb["sample"].startswith("the whole"):
             rec["parity_vs_oracle"] = bool(int(scores[0]) == oracle_score)

@@ -135,3 +135,29 @@ def test_destroy_with_work_in_flight(gpu):
     srv.close()  # drains queued and in-flight rounds, then frees everything
     with pytest.raises(Exception):
         srv.submit(reqs[0])
+
+
+@pytest.mark.parametrize("kind,okind", [(ts.SEMI_GLOBAL, oracle.SEMI_GLOBAL),
+                                        (ts.LOCAL, oracle.LOCAL)], ids=["semi-global", "local"])
+def test_served_kinds_equal_oracle(gpu, kind, okind):
+    # Served rounds of the semi-global and local kinds: whole-triplet jobs and
+    # split requests (their panel bests fold across wavefronts) in one stream.
+    reqs = mixed_requests(33, 200)
+    rng = synth.rng_for(34)
+    reqs += [synth.mutated_triplet(rng, n, 0.05) for n in (600, 520)]
+    want = oracle.score_batch(reqs, kind=okind)
+    srv = ts.Server(max_len=1024, sc=ts.scoring(kind=kind), max_device_bytes=8 << 30)
+    say(f"serving {len(reqs)} requests, kind {kind}")
+    ids = []
+    for k, t in enumerate(reqs):
+        ids.append(srv.submit(t))
+        if k % 50 == 49:
+            time.sleep(0.002)
+    got = []
+    for rid in ids:
+        r = srv.wait(rid, timeout_s=60)
+        assert r["status"] == 0, r
+        got.append(r["score"])
+    srv.close()
+    assert np.array_equal(np.array(got), np.asarray(want)), \
+        [(q, got[q], int(want[q])) for q in range(len(reqs)) if got[q] != want[q]][:5]
