@@ -103,6 +103,20 @@ trioseq_status trioseq_score(const trioseq_triplet* t, const trioseq_scoring* sc
 trioseq_status trioseq_score_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
                                    int32_t* scores, void* hip_stream);
 
+/* Optimal global alignment of one triplet: the traceback (Section II, Eq. 1
+ * for the scores; the alignment is recovered in linear space by Hirschberg's
+ * divide and conquer, which the paper names for its traceback). row0, row1,
+ * row2 (caller buffers of cap chars each) receive S0, S1, S2 as alignment
+ * rows: residues in upper case, '-' for a gap, no terminating NUL; *ncols is
+ * the number of columns and *score the sum-of-pairs score of the alignment,
+ * which is the optimal global score. Requirements: sc->kind ==
+ * TRIOSEQ_GLOBAL, every length <= 16384, cap >= len[0] + len[1] + len[2].
+ * Synchronous; device work runs on hip_stream. On error nothing is written
+ * to the outputs. */
+trioseq_status trioseq_align(const trioseq_triplet* t, const trioseq_scoring* sc, char* row0,
+                             char* row1, char* row2, uint32_t cap, uint32_t* ncols, int32_t* score,
+                             void* hip_stream);
+
 /* ---- Plans: device-resident batches (inputs already in HBM). ---------- */
 
 typedef struct trioseq_plan trioseq_plan;

@@ -82,7 +82,7 @@ class ServeStats(ctypes.Structure):
 EXPORTS = [
     "trioseq_scoring_simple", "trioseq_pack", "trioseq_packed_layout", "trioseq_score",
     "trioseq_score_batch", "trioseq_plan_create", "trioseq_plan_run", "trioseq_plan_get_info",
-    "trioseq_plan_destroy", "trioseq_autotune", "trioseq_serve_create", "trioseq_serve_submit", "trioseq_serve_poll",
+    "trioseq_plan_destroy", "trioseq_autotune", "trioseq_align", "trioseq_serve_create", "trioseq_serve_submit", "trioseq_serve_poll",
     "trioseq_serve_wait", "trioseq_serve_get_stats", "trioseq_serve_destroy",
     "trioseq_last_error", "trioseq_version",
 ]
@@ -137,6 +137,10 @@ def lib() -> ctypes.CDLL:
     L.trioseq_serve_get_stats.restype = st
     L.trioseq_serve_destroy.argtypes = [ctypes.c_void_p]
     L.trioseq_serve_destroy.restype = st
+    L.trioseq_align.argtypes = [P(Triplet), P(Scoring), ctypes.c_char_p, ctypes.c_char_p,
+                                ctypes.c_char_p, ctypes.c_uint32, P(ctypes.c_uint32),
+                                P(ctypes.c_int32), ctypes.c_void_p]
+    L.trioseq_align.restype = st
     L.trioseq_last_error.argtypes = []
     L.trioseq_last_error.restype = ctypes.c_char_p
     L.trioseq_version.argtypes = []
@@ -202,6 +206,21 @@ def score(triplet, sc: Scoring | None = None) -> int:
     out = ctypes.c_int32()
     check(lib().trioseq_score(ctypes.byref(tr), ctypes.byref(sc or _default_scoring()), ctypes.byref(out)))
     return int(out.value)
+
+
+def align(triplet, sc: Scoring | None = None, stream=None):
+    """Optimal global alignment of one triplet: ((row0, row1, row2), score).
+    Rows are strings of upper-case residues and '-' (the traceback)."""
+    keep: list = []
+    tr = _triplet(triplet, keep)
+    cap = max(1, int(tr.len[0]) + int(tr.len[1]) + int(tr.len[2]))
+    rows = [ctypes.create_string_buffer(cap) for _ in range(3)]
+    n = ctypes.c_uint32()
+    sco = ctypes.c_int32()
+    check(lib().trioseq_align(ctypes.byref(tr), ctypes.byref(sc or _default_scoring()), rows[0],
+                              rows[1], rows[2], cap, ctypes.byref(n), ctypes.byref(sco),
+                              _stream_ptr(stream)))
+    return tuple(r.raw[:n.value].decode() for r in rows), int(sco.value)
 
 
 def score_batch(triplets, sc: Scoring | None = None, stream=None) -> np.ndarray:

@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtrioseq.so")
-SOURCES = ["sweep.hip", "api.cpp", "serve.cpp"]
+SOURCES = ["sweep.hip", "traceback.hip", "api.cpp", "serve.cpp", "align.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are kept out of every code object we build.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

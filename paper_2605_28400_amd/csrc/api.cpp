@@ -42,6 +42,8 @@ static const uint8_t* build_code_table() {
 }
 static const uint8_t* g_code = build_code_table();
 
+uint8_t residue_code(char ch) { return g_code[(uint8_t)ch]; }
+
 uint64_t now_ns() {
   return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
              std::chrono::steady_clock::now().time_since_epoch())
@@ -192,6 +194,8 @@ SweepArgs make_sweep_args(const uint32_t* words, const TripletDesc* desc, const 
     a.bnd_tagged[k] = bnd.tagged[k];
   }
   a.red = red;
+  a.plane = nullptr;
+  a.plane_off = nullptr;
   a.sc = sc;
   return a;
 }
@@ -232,6 +236,8 @@ struct trioseq_plan {
   Boundary bnd{};
   int* d_red = nullptr;      // per-triplet reduction pairs (semi-global, local)
   uint32_t red_pairs = 0;
+  int* d_plane = nullptr;          // last-slice planes (traceback plans only)
+  uint64_t* d_plane_off = nullptr;
   // graph replay
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
@@ -254,6 +260,8 @@ static void plan_free(trioseq_plan* p) {
   (void)hipFree(p->d_pface);
   (void)hipFree(p->d_bnd);
   (void)hipFree(p->d_red);
+  (void)hipFree(p->d_plane);
+  (void)hipFree(p->d_plane_off);
   delete p;
 }
 
@@ -309,7 +317,7 @@ namespace trioseq {
 
 trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
                             const trioseq_scoring& sc, const trioseq_plan_options& o, int waves_hint,
-                            Layout* L) {
+                            Layout* L, bool planes) {
   if (n && !lens) return fail(TRIOSEQ_ERR_INVALID_ARG, "lens is NULL");
   if (n > (size_t)INT32_MAX) return fail(TRIOSEQ_ERR_TOO_LARGE, "too many triplets");
   trioseq_status st = validate_scoring(&sc);
@@ -334,6 +342,9 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
       return fail(TRIOSEQ_ERR_TOO_LARGE, "triplet " + std::to_string(t) +
                                              ": every sequence exceeds " +
                                              std::to_string(kMaxSweepLen) + " residues");
+    if (planes && l[0] > (uint32_t)kMaxSweepLen)
+      return fail(TRIOSEQ_ERR_TOO_LARGE, "triplet " + std::to_string(t) + ": sweep sequence exceeds " +
+                                             std::to_string(kMaxSweepLen) + " residues");
     st = check_range(sc, l[0], l[1], l[2], t);
     if (st != TRIOSEQ_OK) return st;
     cells += (double)l[0] * (double)l[1] * (double)l[2];
@@ -354,7 +365,8 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
     const double c = (double)l[0] * l[1] * l[2];
     const bool sp = o.engine == 1 ||
                     (o.engine == -1 && (n == 1 || c >= kSplitCells || c > kSplitFactor * per_wave));
-    AxisChoice ax = sp ? choose_axes_wide(l) : choose_axes_batch(l, ks);
+    // Plane runs keep the caller's axes: the plane is the last slice of S0.
+    AxisChoice ax = planes ? AxisChoice{{0, 1, 2}} : sp ? choose_axes_wide(l) : choose_axes_batch(l, ks);
     TripletDesc& d = L->desc[t];
     for (int a = 0; a < 3; ++a) {
       d.off[a] = off[3 * t + ax.perm[a]];
@@ -380,13 +392,14 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   L->modes = n_split == 0 ? 1 : (n_split == (int)n ? 2 : 3);
   // Whole-triplet-only plans fit four waves per SIMD without much spilling
   // on 4x4 tiles; panel jobs carry tag registers and use the two-wave budget.
-  if (!o.waves_per_simd && L->modes == 1 && ks.rj * ks.rk <= 16) {
+  if (!planes && !o.waves_per_simd && L->modes == 1 && ks.rj * ks.rk <= 16) {
     KernelShape k4 = ks;
     k4.wpe = 4;
     if (shape_supported(k4, sc.kind)) ks = k4;
   }
   L->ks = ks;
   L->kind = sc.kind;
+  L->planes = planes;
   L->panels = panels;
   L->lds_n0 = max_n0;
   L->cells = cells;
@@ -462,7 +475,7 @@ static void remember_tuned(const std::string& key, const trioseq_plan_options& o
 trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested, int* grid,
                            int* waves_per_cu) {
   int w = 0;
-  TRIOSEQ_HIP(sweep_occupancy(L.ks, L.modes, L.kind, L.lds_n0, &w), "occupancy");
+  TRIOSEQ_HIP(sweep_occupancy(L.ks, L.modes, L.kind, L.planes, L.lds_n0, &w), "occupancy");
   int g = requested ? requested : dp.cus * std::max(1, w);
   g = (int)std::min<size_t>((size_t)g, std::max<size_t>(L.jobs.size(), 1));
   *grid = g;
@@ -472,28 +485,31 @@ trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested
 
 }  // namespace trioseq
 
-extern "C" {
-
-trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_off, size_t n,
-                                   const trioseq_scoring* scp, const trioseq_plan_options* opts,
-                                   trioseq_plan** out) {
+// Plans, with or without last-slice planes (traceback): planes = the run
+// also writes triplet t's last slice to the plan's plane buffer at
+// plane_off[t] (plane_ints ints in all).
+static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* word_off, size_t n,
+                                       const trioseq_scoring* scp, const trioseq_plan_options* opts,
+                                       bool planes, const uint64_t* plane_off, uint64_t plane_ints,
+                                       trioseq_plan** out) {
   if (!out) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: plan output is NULL");
   if (!scp) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: scoring is NULL");
   trioseq_plan_options o{-1, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
+  if (planes) o = trioseq_plan_options{-1, 4, 4, 0, 0, 2};  // the plane kernels' shape
   if (!o.tile_rows && !o.tile_cols && !o.waves_per_simd && lens) apply_tuned(lens, n, scp->kind, &o);
   // Inputs are validated (by the layout) before the device is touched; the
   // layout is redone if the device's size changes the split rule's hint.
   Layout L;
   int hint = 256 * kWavesPerCuHint;
-  trioseq_status st = build_layout(lens, word_off, n, *scp, o, hint, &L);
+  trioseq_status st = build_layout(lens, word_off, n, *scp, o, hint, &L, planes);
   if (st != TRIOSEQ_OK) return st;
   DeviceProps dp;
   st = device_props(&dp);
   if (st != TRIOSEQ_OK) return st;
   if (dp.cus * kWavesPerCuHint != hint) {
     hint = dp.cus * kWavesPerCuHint;
-    st = build_layout(lens, word_off, n, *scp, o, hint, &L);
+    st = build_layout(lens, word_off, n, *scp, o, hint, &L, planes);
     if (st != TRIOSEQ_OK) return st;
   }
 
@@ -548,6 +564,16 @@ trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_of
       return hip_bail(e, "hipMalloc panel faces");
     if ((e = hipMemset(p->d_pface, 0, pool_bytes)) != hipSuccess) return hip_bail(e, "hipMemset");
   }
+  if (planes && n) {
+    if ((e = hipMalloc((void**)&p->d_plane, std::max<uint64_t>(plane_ints, 1) * sizeof(int))) !=
+        hipSuccess)
+      return hip_bail(e, "hipMalloc planes");
+    if ((e = hipMalloc((void**)&p->d_plane_off, n * sizeof(uint64_t))) != hipSuccess)
+      return hip_bail(e, "hipMalloc plane offsets");
+    if ((e = hipMemcpy(p->d_plane_off, plane_off, n * sizeof(uint64_t), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return hip_bail(e, "hipMemcpy plane offsets");
+  }
   p->red_pairs = L.red_pairs();
   if (p->red_pairs &&
       (e = hipMalloc((void**)&p->d_red, (uint64_t)p->red_pairs * 2 * sizeof(int))) != hipSuccess)
@@ -569,6 +595,26 @@ trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_of
   return TRIOSEQ_OK;
 }
 
+namespace trioseq {
+
+trioseq_status plan_create_planes(const uint32_t* lens, const uint64_t* off, size_t n,
+                                  const trioseq_scoring& sc, const uint64_t* plane_off,
+                                  uint64_t plane_ints, trioseq_plan** out) {
+  return plan_create_impl(lens, off, n, &sc, nullptr, true, plane_off, plane_ints, out);
+}
+
+const int* plan_planes(const trioseq_plan* p) { return p->d_plane; }
+
+}  // namespace trioseq
+
+extern "C" {
+
+trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_off, size_t n,
+                                   const trioseq_scoring* scp, const trioseq_plan_options* opts,
+                                   trioseq_plan** out) {
+  return plan_create_impl(lens, word_off, n, scp, opts, false, nullptr, 0, out);
+}
+
 static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t* d_scores,
                                hipStream_t s) {
   if (p->n == 0) return hipSuccess;
@@ -578,6 +624,8 @@ static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t
   SweepArgs a = make_sweep_args(d_words, p->d_desc, p->d_jobs, p->njobs, p->lds_n0, d_scores,
                                 p->d_counter, p->d_ctl, p->d_face, p->face_stride, p->d_pface,
                                 p->bnd, p->d_red, p->sc);
+  a.plane = p->d_plane;
+  a.plane_off = p->d_plane_off;
   return launch_sweep(p->ks, p->modes, a, p->grid, s);
 }
 

@@ -18,8 +18,8 @@ trioseq_status fail_hip(hipError_t e, const char* what);
     if (e_ != hipSuccess) return ::trioseq::fail_hip(e_, what); \
   } while (0)
 
-// Residue code of an ASCII character, or 255.
-extern const uint8_t kCode[256];
+// Residue code (0..3 for ACGT in either case) of an ASCII character, or 255.
+uint8_t residue_code(char ch);
 
 trioseq_status validate_scoring(const trioseq_scoring* sc);
 // Checks that the shifted score range of a triplet with these lengths keeps
@@ -59,6 +59,7 @@ SweepArgs make_sweep_args(const uint32_t* words, const TripletDesc* desc, const 
 struct Layout {
   KernelShape ks{4, 4, 2};
   int kind = 0;    // alignment kind of the scoring
+  bool planes = false;  // last-slice planes are written (traceback)
   int modes = 1;   // bit 0 whole-triplet jobs, bit 1 panel jobs
   int engine = 0;  // 0 all whole, 1 all split, 2 mixed
   int panels = 0;
@@ -76,9 +77,10 @@ struct Layout {
 // Validates and lays out n triplets (lens[3t+s], word offsets off[3t+s]).
 // Touches no device state.
 // waves_hint: wavefronts the launch will have (for the split rule).
+// planes: the layout of a traceback plane run (axes kept as given, S0 swept).
 trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
                             const trioseq_scoring& sc, const trioseq_plan_options& o, int waves_hint,
-                            Layout* L);
+                            Layout* L, bool planes = false);
 // Resident wavefronts per compute unit assumed when sizing the split rule.
 constexpr int kWavesPerCuHint = 8;
 // Autotuning cache keyed by a batch's length profile and scoring kind.
@@ -88,5 +90,13 @@ void apply_tuned(const uint32_t* lens, size_t n, int kind, trioseq_plan_options*
 // Waves to launch for a layout on this device.
 trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested, int* grid,
                            int* waves_per_cu);
+
+// Traceback plane runs: a plan over triplets whose runs also write each
+// triplet's last slice (unshifted) to a device buffer of plane_ints ints,
+// triplet t at plane_off[t]; plan_planes gives that buffer.
+trioseq_status plan_create_planes(const uint32_t* lens, const uint64_t* off, size_t n,
+                                  const trioseq_scoring& sc, const uint64_t* plane_off,
+                                  uint64_t plane_ints, trioseq_plan** out);
+const int* plan_planes(const trioseq_plan* p);
 
 }  // namespace trioseq

@@ -94,6 +94,11 @@ struct SweepArgs {
   // red[2t] = best value over the panels folded in so far, red[2t + 1] =
   // panels finished (both reset by k_prepare).
   int* red;
+  // Optional (traceback): triplet t also writes its last slice, M[n0][j][k]
+  // for 0 <= j <= n1, 0 <= k <= n2, unshifted, to plane + plane_off[t] at
+  // index j * (n2 + 1) + k. plane is null when no plane is wanted.
+  int* plane;
+  const uint64_t* plane_off;
   DevScoring sc;
 };
 
@@ -111,10 +116,46 @@ hipError_t launch_prepare(int* ctl, int* counter, int* red, uint32_t nred, hipSt
 // The kernel variant follows a.sc.kind.
 hipError_t launch_sweep(const KernelShape& ks, int modes, const SweepArgs& a, int grid,
                         hipStream_t s);
-hipError_t sweep_occupancy(const KernelShape& ks, int modes, int kind, uint32_t lds_n0,
+// plane: the variant that writes last-slice planes (traceback).
+hipError_t sweep_occupancy(const KernelShape& ks, int modes, int kind, bool plane, uint32_t lds_n0,
                            int* waves_per_cu);
-// Whether kernels of this tile shape exist for this alignment kind.
+// Whether scoring kernels of this tile shape exist for this alignment kind.
+// Plane kernels exist for 4 x 4 tiles at two waves per SIMD, global kind.
 bool shape_supported(const KernelShape& ks, int kind);
+
+// Traceback (traceback.hip). A split box: the forward and reversed planes
+// (ints from the plane buffer base), rows x cols entries each.
+struct SplitDesc {
+  uint64_t fwd, bwd;
+  uint32_t rows, cols;
+};
+// A leaf box: sequence s of the box is residues lo[s] .. lo[s] + len[s] - 1 of
+// the packed sequence at word offset off[s]; its table is scratch + table
+// ((len0+1)(len1+1)(len2+1) ints), its columns go to cols + out (3 bytes per
+// column, at most len0 + len1 + len2 columns).
+struct LeafDesc {
+  uint64_t off[3];
+  uint32_t lo[3];
+  uint32_t len[3];
+  uint64_t table;
+  uint64_t out;
+};
+struct LeafArgs {
+  const uint32_t* words;
+  const LeafDesc* leaves;
+  uint32_t n;
+  int* scratch;
+  uint8_t* cols;
+  uint32_t* ncols;  // per leaf: columns written
+  int32_t* score;   // per leaf: the box's global score
+  int32_t sub[16];
+  int32_t gap;
+};
+// Boxes of at most this many table cells are solved whole by k_leaf.
+constexpr uint64_t kLeafCells = 4096;
+// out[3b] = best F + R of box b, out[3b+1], out[3b+2] = its (p, q).
+hipError_t launch_split(const int* planes, const SplitDesc* boxes, uint32_t n, int* out, hipStream_t s);
+hipError_t launch_leaf(const LeafArgs& a, hipStream_t s);
 
 inline int panel_rows(const KernelShape& ks) { return kGJ * ks.rj; }
 inline int panel_cols(const KernelShape& ks) { return kGK * ks.rk; }

@@ -201,6 +201,9 @@ __device__ __forceinline__ void lds_put(int* p, int v) {
 
 // Global scoring: the lane owning cell (n0, n1, n2) writes the score to
 // score_out (non-null for the triplet's last panel only); returns 0.
+// PLANE kernels (traceback): when plane is non-null every lane keeps its
+// tile of slice n0 in capt (64 * RJ * RK ints of LDS) and, after the sweep,
+// writes its cells unshifted to plane[j * (n2 + 1) + k].
 // Semi-global and local scoring: returns this lane's best unshifted value
 // over the panel's cells that the answer ranges over (the caller reduces).
 //
@@ -213,10 +216,11 @@ __device__ __forceinline__ void lds_put(int* p, int v) {
 // move into the padding that consumes a padding residue scores -128, and the
 // remaining moves mirror moves inside the tensor at gap <= 0); slices outside
 // 0..n0 are excluded from the best and unfloored before slice 0.
-template <int MODE, int KIND, int RJ, int RK>
+template <int MODE, int KIND, bool PLANE, int RJ, int RK>
 __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring& sc,
                            const uint32_t* __restrict__ words, const TripletDesc& td, int pj, int pk,
-                           const PanelIO& io, int32_t* score_out, SplitLds<RJ, RK>* split = nullptr) {
+                           const PanelIO& io, int32_t* score_out, int* plane, int* capt,
+                           SplitLds<RJ, RK>* split = nullptr) {
   constexpr bool WIDE = MODE == kTagged;
   constexpr bool SPC = MODE == kSplitCompute;
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
@@ -706,6 +710,12 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
 #pragma unroll
             for (int cc = 0; cc < RK; ++cc) L.cap[r * RK + cc] = N[r][cc];
         }
+        if (PLANE && plane && t - y - x == n0) {
+#pragma unroll
+          for (int r = 0; r < RJ; ++r)
+#pragma unroll
+            for (int cc = 0; cc < RK; ++cc) capt[lane * (RJ * RK) + r * RK + cc] = N[r][cc];
+        }
       }
 
 #pragma unroll
@@ -721,8 +731,8 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
 
   for (int c = 0; c < nchunks; ++c) {
     if (!SPC) stage_finish(c);
-    const bool cap_chunk =
-        score_out != nullptr && n0 >= c * kChunk - kSkew && n0 <= c * kChunk + kChunk - 1;
+    const bool cap_chunk = (score_out != nullptr || (PLANE && plane != nullptr)) &&
+                           n0 >= c * kChunk - kSkew && n0 <= c * kChunk + kChunk - 1;
     run_chunk(c, cap_chunk, c + 1 < nchunks);
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
@@ -731,6 +741,17 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
   if (own)
     __hip_atomic_store(score_out, L.cap[rsel * RK + csel] + sc.gap2 * (n0 + n1 + n2),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (PLANE && plane) {
+#pragma unroll
+    for (int r = 0; r < RJ; ++r)
+#pragma unroll
+      for (int cc = 0; cc < RK; ++cc) {
+        const int j = j0 + r, k = k0 + cc;
+        if (j <= n1 && k <= n2)
+          plane[(uint64_t)j * (uint64_t)(n2 + 1) + (uint64_t)k] =
+              capt[lane * (RJ * RK) + r * RK + cc] + sc.gap2 * (n0 + j + k);
+      }
+  }
   return KIND == kGlobal ? 0 : best;
 }
 
@@ -932,10 +953,11 @@ __device__ void panel_memory(SplitLds<RJ, RK>& S, const TripletDesc& td, const P
 // moves faces (panel_memory). The workgroup pops jobs from the same queue
 // and in the same dependency order as k_sweep, so the same residency
 // argument holds: every producer was popped earlier by a running workgroup.
-template <int RJ, int RK, int WPE, int KIND>
+template <int RJ, int RK, int WPE, int KIND, bool PLANE>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE))) k_panel(SweepArgs a) {
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
   __shared__ SplitLds<RJ, RK> S;
+  __shared__ int capt[PLANE ? 64 * RJ * RK : 1];
   extern __shared__ uint8_t shb[];
   const int wave = threadIdx.x >> 6;
   const int gen = __hip_atomic_load(a.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -947,6 +969,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
     if (idx >= (int)a.njobs) break;
     const JobDesc jd = a.jobs[idx];
     const TripletDesc td = a.desc[jd.trip];
+    int* plane = PLANE ? a.plane + a.plane_off[jd.trip] : nullptr;
     if (jd.trip != staged) {
       stage_shifts(shb, a.words, td);
       staged = jd.trip;
@@ -976,7 +999,8 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
     int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
     int best = 0;
     if (wave == 0)
-      best = sweep_panel<kSplitCompute, KIND, RJ, RK>(S.L, shb, a.sc, a.words, td, pj, pk, io, so, &S);
+      best = sweep_panel<kSplitCompute, KIND, PLANE, RJ, RK>(S.L, shb, a.sc, a.words, td, pj, pk, io,
+                                                             so, plane, capt, &S);
     else
       panel_memory<RJ, RK>(S, td, io);
     __syncthreads();
@@ -1000,10 +1024,11 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
 //    waves of the grid are resident.
 // MODES: bit 0 = the plan has whole-triplet jobs, bit 1 = panel jobs; a
 // kernel built for one kind only carries no registers for the other.
-template <int RJ, int RK, int WPE, int MODES, int KIND>
+template <int RJ, int RK, int WPE, int MODES, int KIND, bool PLANE>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) k_sweep(SweepArgs a) {
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
   __shared__ Lds<RJ, RK> L;
+  __shared__ int capt[PLANE ? 64 * RJ * RK : 1];
   extern __shared__ uint8_t shb[];
   int* face = a.face + (uint64_t)blockIdx.x * a.face_stride;
   const int gen = __hip_atomic_load(a.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1016,6 +1041,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
     if (idx >= (int)a.njobs) break;
     const JobDesc jd = a.jobs[idx];
     const TripletDesc td = a.desc[jd.trip];
+    int* plane = PLANE ? a.plane + a.plane_off[jd.trip] : nullptr;
     if (jd.trip != staged) {
       stage_shifts(shb, a.words, td);
       staged = jd.trip;
@@ -1039,7 +1065,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
           io.gen = 0;
           io.err = nullptr;
           int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
-          best = max(best, sweep_panel<kPlain, KIND, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk, io, so));
+          best = max(best, sweep_panel<kPlain, KIND, PLANE, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk,
+                                                                    io, so, plane, capt));
         }
       }
       if (KIND != kGlobal) finish_whole(a.scores + td.out, best);
@@ -1058,7 +1085,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       io.gen = gen;
       io.err = a.ctl + 1;
       int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
-      const int best = sweep_panel<kTagged, KIND, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk, io, so);
+      const int best = sweep_panel<kTagged, KIND, PLANE, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk, io,
+                                                                so, plane, capt);
       if (KIND != kGlobal)
         finish_panel(a, jd.trip, td.out, PJ * PK, best);
       else if (so && threadIdx.x == 0 &&
@@ -1107,15 +1135,17 @@ __global__ void k_prepare(int* ctl, int* counter, int* red, uint32_t nred) {
   }
 }
 
-// Kernel variants: tile shape (rows, columns, waves per SIMD) and kind.
-#define TRIOSEQ_SHAPES(X) \
-  X(4, 4, 4, 0) X(4, 4, 2, 0) X(8, 4, 2, 0) X(4, 8, 2, 0) X(4, 4, 2, 1) X(4, 4, 2, 2)
-#define TRIOSEQ_MODES(X, r, c, w, k) X(r, c, w, 1, k) X(r, c, w, 2, k) X(r, c, w, 3, k)
+// Kernel variants: tile shape (rows, columns, waves per SIMD), kind, and
+// whether the last slice is written out (traceback planes).
+#define TRIOSEQ_SHAPES(X)                                                          \
+  X(4, 4, 4, 0, false) X(4, 4, 2, 0, false) X(8, 4, 2, 0, false) X(4, 8, 2, 0, false) \
+  X(4, 4, 2, 1, false) X(4, 4, 2, 2, false) X(4, 4, 2, 0, true)
+#define TRIOSEQ_MODES(X, r, c, w, k, p) X(r, c, w, 1, k, p) X(r, c, w, 2, k, p) X(r, c, w, 3, k, p)
 
 }  // namespace
 
 bool shape_supported(const KernelShape& ks, int kind) {
-#define X(a, b, w, k) if (ks.rj == a && ks.rk == b && ks.wpe == w && kind == k) return true;
+#define X(a, b, w, k, p) if (!p && ks.rj == a && ks.rk == b && ks.wpe == w && kind == k) return true;
   TRIOSEQ_SHAPES(X)
 #undef X
   return false;
@@ -1140,30 +1170,31 @@ hipError_t launch_sweep(const KernelShape& ks, int modes, const SweepArgs& a, in
                         hipStream_t s) {
   const size_t lds = shift_lds_bytes(a.lds_n0);
   const int kind = a.sc.kind;
-#define Y(r, c, w, m, k)                                                               \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m && kind == k) {            \
-    if (m == 2)                                                                        \
-      hipLaunchKernelGGL((k_panel<r, c, w, k>), dim3(grid), dim3(128), lds, s, a);     \
-    else                                                                               \
-      hipLaunchKernelGGL((k_sweep<r, c, w, m, k>), dim3(grid), dim3(64), lds, s, a);   \
-    return hipGetLastError();                                                          \
+  const bool plane = a.plane != nullptr;
+#define Y(r, c, w, m, k, p)                                                                     \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m && kind == k && plane == p) {       \
+    if (m == 2)                                                                                 \
+      hipLaunchKernelGGL((k_panel<r, c, w, k, p>), dim3(grid), dim3(128), lds, s, a);           \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_sweep<r, c, w, m, k, p>), dim3(grid), dim3(64), lds, s, a);         \
+    return hipGetLastError();                                                                   \
   }
-#define X(r, c, w, k) TRIOSEQ_MODES(Y, r, c, w, k)
+#define X(r, c, w, k, p) TRIOSEQ_MODES(Y, r, c, w, k, p)
   TRIOSEQ_SHAPES(X)
 #undef X
 #undef Y
   return hipErrorInvalidValue;
 }
 
-hipError_t sweep_occupancy(const KernelShape& ks, int modes, int kind, uint32_t lds_n0,
+hipError_t sweep_occupancy(const KernelShape& ks, int modes, int kind, bool plane, uint32_t lds_n0,
                            int* waves_per_cu) {
-#define Y(r, c, w, m, k)                                                                          \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m && kind == k)                         \
-    return m == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, k_panel<r, c, w, k>, \
-                                                                 128, shift_lds_bytes(lds_n0))      \
+#define Y(r, c, w, m, k, p)                                                                       \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m && kind == k && plane == p)           \
+    return m == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                 \
+                        waves_per_cu, k_panel<r, c, w, k, p>, 128, shift_lds_bytes(lds_n0))       \
                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                 \
-                        waves_per_cu, k_sweep<r, c, w, m, k>, 64, shift_lds_bytes(lds_n0));
-#define X(r, c, w, k) TRIOSEQ_MODES(Y, r, c, w, k)
+                        waves_per_cu, k_sweep<r, c, w, m, k, p>, 64, shift_lds_bytes(lds_n0));
+#define X(r, c, w, k, p) TRIOSEQ_MODES(Y, r, c, w, k, p)
   TRIOSEQ_SHAPES(X)
 #undef X
 #undef Y

@@ -134,3 +134,21 @@ def test_bad_kinds_rejected():
                                          ctypes.byref(h)) == -1
     assert ts.KINDS == {"global": 0, "semi-global": 1, "local": 2}
     assert ts.scoring(kind="local").kind == ts.LOCAL
+
+
+def test_align_rejects_bad_input_before_device_work():
+    L = ts.lib()
+    keep = []
+    tr = ts._triplet(("ACG", "AC", "G"), keep)
+    rows = [ctypes.create_string_buffer(8) for _ in range(3)]
+    n, sco = ctypes.c_uint32(77), ctypes.c_int32(123)
+    args = lambda sc, cap: (ctypes.byref(tr), ctypes.byref(sc), rows[0], rows[1], rows[2], cap,
+                            ctypes.byref(n), ctypes.byref(sco), None)
+    assert L.trioseq_align(*args(ts.scoring(kind=ts.LOCAL), 8)) == -1      # global only
+    assert L.trioseq_align(*args(ts.scoring(), 5)) == -1                   # cap < 3 + 2 + 1
+    assert L.trioseq_align(None, ctypes.byref(ts.scoring()), rows[0], rows[1], rows[2], 8,
+                           ctypes.byref(n), ctypes.byref(sco), None) == -1
+    bad = ts._triplet(("ACX", "A", "A"), keep)
+    assert L.trioseq_align(ctypes.byref(bad), ctypes.byref(ts.scoring()), rows[0], rows[1], rows[2],
+                           8, ctypes.byref(n), ctypes.byref(sco), None) == -2
+    assert n.value == 77 and sco.value == 123  # untouched on error
