@@ -32,7 +32,7 @@ PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_PER_CELL_OF = {"global": 7, "semi-global": 7, "local": 9}
 OPS_PER_CELL = OPS_PER_CELL_OF["global"]
 
-WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served")
+WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served", "traceback")
 
 # HBM bytes per launch of the sweep kernel, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE runs scaled by the same counters on a plain 1 GiB copy (summaries
@@ -237,6 +237,49 @@ def served(args):
     print(json.dumps(rec), flush=True)
 
 
+def traceback(args):
+    """Optimal alignments (trioseq_align): the 1024 x 1000 x 1048 triplet,
+    timed over K synchronous calls, and a batch of 100,000 length-8 triplets
+    (the size the paper's traceback was measured at) through
+    trioseq_align_batch. Cells are a*b*c of the aligned triplets."""
+    import torch
+    import paper_2605_28400_amd as ts
+    from paper_2605_28400_amd import synth
+    t = synth.single_1k().triplets[0]
+    cells = float(synth.cells(t))
+    for _ in range(args.warmup):
+        ts.align(t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rows, score = ts.align(t)
+    wall = (time.perf_counter() - t0) / args.steps
+    rng = synth.rng_for(6)
+    short = [synth.mutated_triplet(rng, 8, 0.2, lens=(8, 8, 8)) for _ in range(100_000)]
+    ts.align_batch(short[:1000])
+    t0 = time.perf_counter()
+    res = ts.align_batch(short)
+    bwall = time.perf_counter() - t0
+    achieved = cells * OPS_PER_CELL / wall / 1e12
+    rec = {
+        "metric": "GCUPS", "value": round(cells / wall / 1e9, 3), "unit": "GCUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "traceback_single_1024x1000x1048", "call": "trioseq_align (host rows)",
+                   "columns": len(rows[0]), "score": score, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 2),
+                     "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
+                     "ops_per_cell": OPS_PER_CELL,
+                     "kernel": "whole call (plane sweeps of every level, splits, leaves, copies)"},
+        "batch_len8": {"triplets": len(short), "seconds": round(bwall, 4),
+                       "alignments_per_s": round(len(short) / bwall, 1),
+                       "gcups": round(512 * len(short) / bwall / 1e9, 4),
+                       "call": "trioseq_align_batch (host rows)"},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def copy_calibration(mib: int) -> None:
     """A plain device-to-device copy of known size: reads and writes mib MiB per launch,
     so a byte counter's reading for it gives the counter's scale factor."""
@@ -255,11 +298,11 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.workload == "served":
+    if args.workload in ("served", "traceback"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only.", file=sys.stderr)
             sys.exit(2)
-        served(args)
+        (served if args.workload == "served" else traceback)(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: every workload here is measured on a single "

@@ -117,6 +117,16 @@ trioseq_status trioseq_align(const trioseq_triplet* t, const trioseq_scoring* sc
                              char* row1, char* row2, uint32_t cap, uint32_t* ncols, int32_t* score,
                              void* hip_stream);
 
+/* Optimal global alignments of n triplets, computed together (each level's
+ * plane runs and all small sub-problems of the batch share launches). rows is
+ * one caller buffer of 3 * sum_t cap_t chars, cap_t = len[0] + len[1] +
+ * len[2] of triplet t; row s of triplet t occupies the cap_t chars at
+ * rows + 3 * (cap_0 + ... + cap_{t-1}) + s * cap_t, its first ncols[t]
+ * filled as in trioseq_align (no NULs). scores[t] is the optimal global
+ * score. Requirements as trioseq_align. On error nothing is written. */
+trioseq_status trioseq_align_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
+                                   char* rows, uint32_t* ncols, int32_t* scores, void* hip_stream);
+
 /* ---- Plans: device-resident batches (inputs already in HBM). ---------- */
 
 typedef struct trioseq_plan trioseq_plan;

@@ -82,7 +82,7 @@ class ServeStats(ctypes.Structure):
 EXPORTS = [
     "trioseq_scoring_simple", "trioseq_pack", "trioseq_packed_layout", "trioseq_score",
     "trioseq_score_batch", "trioseq_plan_create", "trioseq_plan_run", "trioseq_plan_get_info",
-    "trioseq_plan_destroy", "trioseq_autotune", "trioseq_align", "trioseq_serve_create", "trioseq_serve_submit", "trioseq_serve_poll",
+    "trioseq_plan_destroy", "trioseq_autotune", "trioseq_align", "trioseq_align_batch", "trioseq_serve_create", "trioseq_serve_submit", "trioseq_serve_poll",
     "trioseq_serve_wait", "trioseq_serve_get_stats", "trioseq_serve_destroy",
     "trioseq_last_error", "trioseq_version",
 ]
@@ -141,6 +141,9 @@ def lib() -> ctypes.CDLL:
                                 ctypes.c_char_p, ctypes.c_uint32, P(ctypes.c_uint32),
                                 P(ctypes.c_int32), ctypes.c_void_p]
     L.trioseq_align.restype = st
+    L.trioseq_align_batch.argtypes = [P(Triplet), ctypes.c_size_t, P(Scoring), ctypes.c_char_p,
+                                      P(ctypes.c_uint32), P(ctypes.c_int32), ctypes.c_void_p]
+    L.trioseq_align_batch.restype = st
     L.trioseq_last_error.argtypes = []
     L.trioseq_last_error.restype = ctypes.c_char_p
     L.trioseq_version.argtypes = []
@@ -221,6 +224,33 @@ def align(triplet, sc: Scoring | None = None, stream=None):
                               rows[1], rows[2], cap, ctypes.byref(n), ctypes.byref(sco),
                               _stream_ptr(stream)))
     return tuple(r.raw[:n.value].decode() for r in rows), int(sco.value)
+
+
+def align_batch(triplets, sc: Scoring | None = None, stream=None) -> list:
+    """Optimal global alignments of many triplets, computed together:
+    a list of ((row0, row1, row2), score)."""
+    keep: list = []
+    n = len(triplets)
+    arr = (Triplet * max(n, 1))()
+    caps = []
+    for q, t in enumerate(triplets):
+        arr[q] = _triplet(t, keep)
+        caps.append(int(arr[q].len[0]) + int(arr[q].len[1]) + int(arr[q].len[2]))
+    buf = ctypes.create_string_buffer(max(1, 3 * sum(caps)))
+    ncols = np.zeros(max(n, 1), dtype=np.uint32)
+    scores = np.zeros(max(n, 1), dtype=np.int32)
+    check(lib().trioseq_align_batch(arr, n, ctypes.byref(sc or _default_scoring()), buf,
+                                    ncols.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                    scores.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    _stream_ptr(stream)))
+    raw = buf.raw
+    out, base = [], 0
+    for q in range(n):
+        c, k = caps[q], int(ncols[q])
+        out.append((tuple(raw[base + a * c: base + a * c + k].decode() for a in range(3)),
+                    int(scores[q])))
+        base += 3 * c
+    return out
 
 
 def score_batch(triplets, sc: Scoring | None = None, stream=None) -> np.ndarray:

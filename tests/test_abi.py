@@ -152,3 +152,16 @@ def test_align_rejects_bad_input_before_device_work():
     assert L.trioseq_align(ctypes.byref(bad), ctypes.byref(ts.scoring()), rows[0], rows[1], rows[2],
                            8, ctypes.byref(n), ctypes.byref(sco), None) == -2
     assert n.value == 77 and sco.value == 123  # untouched on error
+
+
+def test_align_batch_rejects_bad_input():
+    L = ts.lib()
+    n, s = ctypes.c_uint32(), ctypes.c_int32()
+    assert L.trioseq_align_batch(None, 1, ctypes.byref(ts.scoring()), None, ctypes.byref(n),
+                                 ctypes.byref(s), None) == -1
+    keep = []
+    arr = (ts.Triplet * 1)(ts._triplet(("AC", "A", "G"), keep))
+    buf = ctypes.create_string_buffer(12)
+    assert L.trioseq_align_batch(arr, 1, ctypes.byref(ts.scoring(kind=ts.SEMI_GLOBAL)), buf,
+                                 ctypes.byref(n), ctypes.byref(s), None) == -1
+    assert ts.align_batch([]) == []

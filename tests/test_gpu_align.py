@@ -106,3 +106,30 @@ def test_single_1k_matches_golden(gpu):
     say("align single_1k")
     rows, score = ts.align(t)
     check_alignment(t, rows, score, want=int(g["scores"][0]))
+
+
+def test_batch_equals_single_calls(gpu):
+    # Fuzz shapes, related triplets and one large triplet in one batch: every
+    # result valid and equal to the triplet aligned alone.
+    rng = np.random.default_rng(66)
+    trips = synth.fuzz(seed=66, count=30, max_len=40)
+    trips += [synth.mutated_triplet(rng, int(n), 0.1) for n in (90, 260)]
+    say(f"align batch n={len(trips)}")
+    got = ts.align_batch(trips)
+    want = oracle.score_batch(trips)
+    for q, (t, (rows, score)) in enumerate(zip(trips, got)):
+        check_alignment(t, rows, score, want=int(want[q]))
+    for q in (0, 7, len(trips) - 2, len(trips) - 1):
+        assert ts.align(trips[q]) == got[q]
+
+
+def test_batch_of_length_8(gpu):
+    # The traceback size the paper measures: many triplets of length 8.
+    rng = np.random.default_rng(67)
+    trips = [synth.mutated_triplet(rng, 8, 0.2, lens=(8, 8, 8)) for _ in range(3000)]
+    say("align batch of 3000 x length 8")
+    got = ts.align_batch(trips)
+    want = oracle.score_batch(trips)
+    for q in range(0, len(trips), 7):
+        check_alignment(trips[q], got[q][0], got[q][1], want=int(want[q]))
+    assert [s for _, s in got] == [int(v) for v in want]
