@@ -69,7 +69,7 @@ typedef enum trioseq_kind {
  * gap against gap always scores 0. Limits: every sub[x][y] - 2*gap lies in
  * [-127, 127] (the kernels keep these terms as bytes); SEMI_GLOBAL and LOCAL
  * need gap <= 0. kind is a trioseq_kind; semi-global and local plans support
- * the default 4 x 4 lane tile at 2 waves per SIMD only. */
+ * 4 x 4 (the default) and 8 x 4 lane tiles at 2 waves per SIMD. */
 typedef struct trioseq_scoring {
   int32_t sub[4][4];
   int32_t gap;

@@ -1096,9 +1096,6 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
   }
 }
 
-// Sentinel faces for panels on the tensor edge: every entry kSent, except
-// the seeded top face, whose entry for k = 0 at slice 0 is 0 (it makes
-// M'(0,0,0) = 0 through the move from the virtual row above).
 // Sentinel faces for panels on the tensor edge, in the plain layout (one
 // int per entry) and the tagged layout (value, kTagAlways). Every value is
 // kSent except the seeded top faces' entry for k = 0 at slice 0, which is 0
@@ -1139,7 +1136,8 @@ __global__ void k_prepare(int* ctl, int* counter, int* red, uint32_t nred) {
 // whether the last slice is written out (traceback planes).
 #define TRIOSEQ_SHAPES(X)                                                          \
   X(4, 4, 4, 0, false) X(4, 4, 2, 0, false) X(8, 4, 2, 0, false) X(4, 8, 2, 0, false) \
-  X(4, 4, 2, 1, false) X(4, 4, 2, 2, false) X(4, 4, 2, 0, true)
+  X(4, 4, 2, 1, false) X(4, 4, 2, 2, false) X(8, 4, 2, 1, false) X(8, 4, 2, 2, false) \
+  X(4, 4, 2, 0, true)
 #define TRIOSEQ_MODES(X, r, c, w, k, p) X(r, c, w, 1, k, p) X(r, c, w, 2, k, p) X(r, c, w, 3, k, p)
 
 }  // namespace

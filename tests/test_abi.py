@@ -123,12 +123,12 @@ def test_bad_kinds_rejected():
     # Semi-global and local scoring need gap <= 0.
     for kind in (ts.SEMI_GLOBAL, ts.LOCAL):
         assert _status(lambda: ts.score(("A", "C", "G"), ts.scoring(2, -1, gap=1, kind=kind))) == -1
-    # ... and the default 4 x 4 tile at two waves per SIMD.
+    # ... and 4 x 4 or 8 x 4 tiles at two waves per SIMD.
     lens = np.array([3, 3, 3], dtype=np.uint32)
     h = ctypes.c_void_p()
     for kind in (ts.SEMI_GLOBAL, ts.LOCAL):
-        for opts in [ts.PlanOptions(-1, 8, 4, 0, 0, 2), ts.PlanOptions(-1, 4, 8, 0, 0, 2),
-                     ts.PlanOptions(-1, 4, 4, 0, 0, 4)]:
+        for opts in [ts.PlanOptions(-1, 4, 8, 0, 0, 2), ts.PlanOptions(-1, 4, 4, 0, 0, 4),
+                     ts.PlanOptions(-1, 8, 4, 0, 0, 4)]:
             assert L.trioseq_plan_create(lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), None,
                                          1, ctypes.byref(ts.scoring(kind=kind)), ctypes.byref(opts),
                                          ctypes.byref(h)) == -1

@@ -36,9 +36,10 @@ def torch_cuda():
     return torch
 
 
-def run_plan(torch, trips, sc, engine=-1, use_graph=False, reps=1, grid=0):
+def run_plan(torch, trips, sc, engine=-1, use_graph=False, reps=1, grid=0, tile=(0, 0)):
     lens, off, words = ts.pack_batch(trips)
-    plan = ts.Plan(lens, off, sc=sc, engine=engine, use_graph=use_graph, grid=grid)
+    plan = ts.Plan(lens, off, sc=sc, engine=engine, use_graph=use_graph, grid=grid, tile=tile,
+                   waves_per_simd=2 if tile != (0, 0) else 0)
     d_words = torch.from_numpy(words.view(np.int32)).cuda()
     outs = []
     for _ in range(reps):
@@ -76,15 +77,21 @@ def test_single_small_fuzz(torch_cuda, name, kind, okind):
         assert ts.score(t, sc) == want[q], (q, [s.size for s in t])
 
 
+@pytest.mark.parametrize("tile", [(4, 4), (8, 4)], ids=["4x4", "8x4"])
 @pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
-def test_batch_whole_triplets(torch_cuda, name, kind, okind):
+def test_batch_whole_triplets(torch_cuda, name, kind, okind, tile):
     rng = np.random.default_rng(42)
     trips = synth.fuzz(seed=42, count=60, max_len=90) + related(rng, 60, 1, 120)
     want = want_of(trips, okind)
-    say(f"{name} batch whole n={len(trips)}")
-    got, info = run_plan(torch_cuda, trips, ts.scoring(kind=kind), engine=0)
-    assert info["engine"] == 0
+    say(f"{name} batch whole n={len(trips)} tile={tile}")
+    got, info = run_plan(torch_cuda, trips, ts.scoring(kind=kind), engine=0, tile=tile)
+    assert info["engine"] == 0 and (info["tile_rows"], info["tile_cols"]) == tile
     assert (got == want).all(), report(trips, got, want)
+    # Split and mixed plans of the same tile shape.
+    got1, info1 = run_plan(torch_cuda, related(rng, 1, 200, 200) + trips[:20], ts.scoring(kind=kind),
+                           tile=tile)
+    assert info1["engine"] == 2
+    assert (got1[1:] == want[:20]).all()
 
 
 @pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
