@@ -39,9 +39,9 @@ WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served", "tr
 # with the commands are under profiles/). Each figure holds only for the kernel
 # source it was measured on; for any other source the field is null.
 TRAFFIC = {
-    "single_1024x1000x1048": (1.5629e9, "330a41ad2001568d"),
-    "batch_8192_len100-400": (7.2385e10, "330a41ad2001568d"),
-    "single_4096x4000x4150": (7.8966e10, "330a41ad2001568d"),
+    "single_1024x1000x1048": (1.5689e9, "5b986628d09c52c4"),
+    "batch_8192_len100-400": (7.2410e10, "5b986628d09c52c4"),
+    "single_4096x4000x4150": (7.9174e10, "5b986628d09c52c4"),
 }
 
 
