@@ -53,7 +53,7 @@ uint64_t pack_range(const std::vector<uint8_t>& codes, uint32_t from, uint32_t t
 
 trioseq_status hip_err(hipError_t e, const char* what) { return fail_hip(e, what); }
 
-// Leaves solved per k_leaf launch (bounds the scratch tables: 16 KiB each).
+// Leaves solved per k_leaf launch (bounds the column buffers of a launch).
 constexpr size_t kLeavesPerLaunch = 1 << 18;
 
 // One level: every box in `boxes` is split; its two children go to `next`.
@@ -67,6 +67,7 @@ trioseq_status split_level(const std::vector<Box>& boxes, const std::vector<std:
   std::vector<uint32_t> lens(6 * nb), words;
   std::vector<uint64_t> offs(6 * nb), poff(2 * nb);
   std::vector<SplitDesc> sd(nb);
+  std::vector<uint32_t> chunk_box;
   std::vector<int> axes(3 * nb);
   std::vector<uint32_t> mids(nb);
   uint64_t pints = 0;
@@ -97,26 +98,33 @@ trioseq_status split_level(const std::vector<Box>& boxes, const std::vector<std:
     pints += (uint64_t)prow * pcol;
     poff[2 * q + 1] = pints;
     pints += (uint64_t)prow * pcol;
-    sd[q] = SplitDesc{poff[2 * q], poff[2 * q + 1], prow, pcol};
+    const uint32_t nchunk = (uint32_t)(((uint64_t)prow * pcol + kSplitChunk - 1) / kSplitChunk);
+    sd[q] = SplitDesc{poff[2 * q], poff[2 * q + 1], prow, pcol, (uint32_t)chunk_box.size(), nchunk};
+    chunk_box.insert(chunk_box.end(), nchunk, (uint32_t)q);
   }
   trioseq_plan* plan = nullptr;
   trioseq_status st = plan_create_planes(lens.data(), offs.data(), 2 * nb, sc, poff.data(), pints, &plan);
   if (st != TRIOSEQ_OK) return st;
-  DevBuf d_words, d_scores, d_sd, d_out;
+  DevBuf d_words, d_scores, d_sd, d_out, d_chunk_box, d_partial;
   std::vector<int> out(3 * nb);
+  const size_t nchunks = chunk_box.size();
   hipError_t e;
   if ((e = d_words.alloc(words.size() * 4)) != hipSuccess || (e = d_scores.alloc(2 * nb * 4)) != hipSuccess ||
       (e = d_sd.alloc(nb * sizeof(SplitDesc))) != hipSuccess || (e = d_out.alloc(3 * nb * 4)) != hipSuccess ||
+      (e = d_chunk_box.alloc(nchunks * 4)) != hipSuccess || (e = d_partial.alloc(nchunks * 8)) != hipSuccess ||
       (e = hipMemcpyAsync(d_words.p, words.data(), words.size() * 4, hipMemcpyHostToDevice, s)) !=
           hipSuccess ||
       (e = hipMemcpyAsync(d_sd.p, sd.data(), nb * sizeof(SplitDesc), hipMemcpyHostToDevice, s)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(d_chunk_box.p, chunk_box.data(), nchunks * 4, hipMemcpyHostToDevice, s)) !=
           hipSuccess) {
     trioseq_plan_destroy(plan);
     return hip_err(e, "align: plane batch");
   }
   st = trioseq_plan_run(plan, d_words.as<uint32_t>(), d_scores.as<int32_t>(), s);
   if (st == TRIOSEQ_OK) {
-    e = launch_split(plan_planes(plan), d_sd.as<SplitDesc>(), (uint32_t)nb, d_out.as<int>(), s);
+    e = launch_split(plan_planes(plan), d_sd.as<SplitDesc>(), (uint32_t)nb, d_chunk_box.as<uint32_t>(),
+                     (uint32_t)nchunks, d_partial.as<int>(), d_out.as<int>(), s);
     if (e == hipSuccess) e = hipMemcpyAsync(out.data(), d_out.p, 3 * nb * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) st = hip_err(e, "align: split");
@@ -151,34 +159,32 @@ trioseq_status solve_leaves(const std::vector<Box>& leaves, size_t first, size_t
                             std::vector<uint8_t>& cols, std::vector<uint32_t>& ncols,
                             std::vector<int32_t>& lscore, hipStream_t s) {
   ld.assign(n, LeafDesc{});
-  uint64_t table_ints = 0, col_bytes = 0;
+  uint64_t col_bytes = 0;
   for (size_t q = 0; q < n; ++q) {
     const Box& b = leaves[first + q];
+    if (b.cells() > kLeafCells) return fail(TRIOSEQ_ERR_DEVICE, "align: leaf larger than its table");
     for (int a = 0; a < 3; ++a) {
       ld[q].off[a] = soff[3 * b.trip + a];
       ld[q].lo[a] = b.lo[a];
       ld[q].len[a] = b.hi[a] - b.lo[a];
     }
-    ld[q].table = table_ints;
     ld[q].out = col_bytes;
-    table_ints += b.cells();
     col_bytes += 3ull * (ld[q].len[0] + ld[q].len[1] + ld[q].len[2]);
   }
   cols.assign(col_bytes, 0);
   ncols.assign(n, 0);
   lscore.assign(n, 0);
-  DevBuf d_words, d_leaves, d_scratch, d_cols, d_ncols, d_lscore;
+  DevBuf d_words, d_leaves, d_cols, d_ncols, d_lscore;
   hipError_t e;
   if ((e = d_words.alloc(words.size() * 4)) != hipSuccess ||
       (e = d_leaves.alloc(n * sizeof(LeafDesc))) != hipSuccess ||
-      (e = d_scratch.alloc(table_ints * 4)) != hipSuccess || (e = d_cols.alloc(col_bytes)) != hipSuccess ||
+      (e = d_cols.alloc(col_bytes)) != hipSuccess ||
       (e = d_ncols.alloc(n * 4)) != hipSuccess || (e = d_lscore.alloc(n * 4)) != hipSuccess)
     return hip_err(e, "align: leaf buffers");
   LeafArgs la;
   la.words = d_words.as<uint32_t>();
   la.leaves = d_leaves.as<LeafDesc>();
   la.n = (uint32_t)n;
-  la.scratch = d_scratch.as<int>();
   la.cols = d_cols.as<uint8_t>();
   la.ncols = d_ncols.as<uint32_t>();
   la.score = d_lscore.as<int32_t>();

@@ -472,10 +472,36 @@ static void remember_tuned(const std::string& key, const trioseq_plan_options& o
   g_tuned.emplace_back(key, o);
 }
 
+// Occupancy per (device, kernel variant, dynamic LDS bytes): the runtime
+// query costs about 0.2 ms, and plans of one process ask the same few.
+static std::mutex g_occ_mu;
+static std::vector<std::pair<std::string, int>> g_occ;
+
+static hipError_t cached_occupancy(const Layout& L, int device, int* w) {
+  const std::string key = std::to_string(device) + "/" + std::to_string(L.ks.rj) + "x" +
+                          std::to_string(L.ks.rk) + "/" + std::to_string(L.ks.wpe) + "/" +
+                          std::to_string(L.modes) + "/" + std::to_string(L.kind) + "/" +
+                          std::to_string((int)L.planes) + "/" + std::to_string(shift_lds_bytes(L.lds_n0));
+  {
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    for (const auto& kv : g_occ)
+      if (kv.first == key) {
+        *w = kv.second;
+        return hipSuccess;
+      }
+  }
+  hipError_t e = sweep_occupancy(L.ks, L.modes, L.kind, L.planes, L.lds_n0, w);
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    g_occ.emplace_back(key, *w);
+  }
+  return e;
+}
+
 trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested, int* grid,
                            int* waves_per_cu) {
   int w = 0;
-  TRIOSEQ_HIP(sweep_occupancy(L.ks, L.modes, L.kind, L.planes, L.lds_n0, &w), "occupancy");
+  TRIOSEQ_HIP(cached_occupancy(L, dp.device, &w), "occupancy");
   int g = requested ? requested : dp.cus * std::max(1, w);
   g = (int)std::min<size_t>((size_t)g, std::max<size_t>(L.jobs.size(), 1));
   *grid = g;

@@ -124,27 +124,28 @@ hipError_t sweep_occupancy(const KernelShape& ks, int modes, int kind, bool plan
 bool shape_supported(const KernelShape& ks, int kind);
 
 // Traceback (traceback.hip). A split box: the forward and reversed planes
-// (ints from the plane buffer base), rows x cols entries each.
+// (ints from the plane buffer base), rows x cols entries each, reduced in
+// nchunk chunks of kSplitChunk cells numbered from chunk0.
+constexpr uint32_t kSplitChunk = 16384;
 struct SplitDesc {
   uint64_t fwd, bwd;
   uint32_t rows, cols;
+  uint32_t chunk0, nchunk;
 };
 // A leaf box: sequence s of the box is residues lo[s] .. lo[s] + len[s] - 1 of
-// the packed sequence at word offset off[s]; its table is scratch + table
-// ((len0+1)(len1+1)(len2+1) ints), its columns go to cols + out (3 bytes per
-// column, at most len0 + len1 + len2 columns).
+// the packed sequence at word offset off[s]; (len0+1)(len1+1)(len2+1) <=
+// kLeafCells; its columns go to cols + out (3 bytes per column, at most
+// len0 + len1 + len2 columns).
 struct LeafDesc {
   uint64_t off[3];
   uint32_t lo[3];
   uint32_t len[3];
-  uint64_t table;
   uint64_t out;
 };
 struct LeafArgs {
   const uint32_t* words;
   const LeafDesc* leaves;
   uint32_t n;
-  int* scratch;
   uint8_t* cols;
   uint32_t* ncols;  // per leaf: columns written
   int32_t* score;   // per leaf: the box's global score
@@ -154,7 +155,9 @@ struct LeafArgs {
 // Boxes of at most this many table cells are solved whole by k_leaf.
 constexpr uint64_t kLeafCells = 4096;
 // out[3b] = best F + R of box b, out[3b+1], out[3b+2] = its (p, q).
-hipError_t launch_split(const int* planes, const SplitDesc* boxes, uint32_t n, int* out, hipStream_t s);
+// chunk_box[c] = the box of chunk c; partial: 2 ints per chunk.
+hipError_t launch_split(const int* planes, const SplitDesc* boxes, uint32_t n, const uint32_t* chunk_box,
+                        uint32_t nchunks, int* partial, int* out, hipStream_t s);
 hipError_t launch_leaf(const LeafArgs& a, hipStream_t s);
 
 inline int panel_rows(const KernelShape& ks) { return kGJ * ks.rj; }

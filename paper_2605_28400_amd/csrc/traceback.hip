@@ -7,9 +7,9 @@
 // first half, F[p][q], and of the tensor of the reversed second half,
 // R[p'][q'], over the two other axes. Every optimal alignment of the box
 // crosses the slice mid at some (p, q) with F[p][q] + R[P-p][Q-q] equal to
-// the box's score, so k_split picks such a cell and the box becomes two.
-// Boxes of at most kLeafCells cells are solved by k_leaf: the full table of
-// the box and a walk back from its far corner.
+// the box's score, so the split kernels pick such a cell and the box becomes
+// two. Boxes of at most kLeafCells cells are solved by k_leaf: the full
+// table of the box in LDS and a walk back from its far corner.
 #include "internal.h"
 
 namespace trioseq {
@@ -20,25 +20,28 @@ __device__ __forceinline__ uint32_t leaf_residue(const uint32_t* __restrict__ wo
   return (words[off + (p >> 4)] >> ((p & 15u) << 1)) & 3u;
 }
 
-// One workgroup per box: the best F[p][q] + R[P-p][Q-q] over the plane, ties
-// broken towards the smallest p * cols + q (so the choice is deterministic).
-__global__ void __launch_bounds__(256) k_split(const int* __restrict__ planes,
-                                               const SplitDesc* __restrict__ boxes, uint32_t n,
-                                               int* __restrict__ out) {
+// Split, stage 1: one workgroup per chunk of kSplitChunk cells of one box's
+// plane; its best F[p][q] + R[P-p][Q-q] and the smallest linear index
+// p * cols + q reaching it.
+__global__ void __launch_bounds__(256) k_split_part(const int* __restrict__ planes,
+                                                    const SplitDesc* __restrict__ boxes,
+                                                    const uint32_t* __restrict__ chunk_box,
+                                                    uint32_t nchunks, int* __restrict__ partial) {
   __shared__ int s_val[256];
   __shared__ uint32_t s_idx[256];
-  const uint32_t b = blockIdx.x;
-  if (b >= n) return;
-  const SplitDesc d = boxes[b];
+  const uint32_t ch = blockIdx.x;
+  if (ch >= nchunks) return;
+  const SplitDesc d = boxes[chunk_box[ch]];
   const int* F = planes + d.fwd;
   const int* R = planes + d.bwd;
   const uint32_t cells = d.rows * d.cols;
+  const uint32_t lo = (ch - d.chunk0) * kSplitChunk;
+  const uint32_t hi = min(cells, lo + kSplitChunk);
   int best = INT32_MIN;
   uint32_t bidx = 0xFFFFFFFFu;
-  for (uint32_t q = threadIdx.x; q < cells; q += blockDim.x) {
+  for (uint32_t q = lo + threadIdx.x; q < hi; q += blockDim.x) {
     const uint32_t p = q / d.cols, c = q - p * d.cols;
-    const uint32_t rq = (d.rows - 1 - p) * d.cols + (d.cols - 1 - c);
-    const int v = F[q] + R[rq];
+    const int v = F[q] + R[(d.rows - 1 - p) * d.cols + (d.cols - 1 - c)];
     if (v > best) {  // q grows, so the first maximum of this thread is kept
       best = v;
       bidx = q;
@@ -59,59 +62,96 @@ __global__ void __launch_bounds__(256) k_split(const int* __restrict__ planes,
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[3 * b] = s_val[0];
-    out[3 * b + 1] = (int)(s_idx[0] / d.cols);
-    out[3 * b + 2] = (int)(s_idx[0] % d.cols);
+    partial[2 * ch] = s_val[0];
+    partial[2 * ch + 1] = (int)s_idx[0];
   }
 }
 
-// One thread per leaf box: the table of Eq. 1 over the box (global
-// initialisation: the box's corner is 0, moves leaving the box do not exist),
-// then the walk back from the far corner, taking at every cell the first
-// move, in a fixed order, whose predecessor plus column score gives the
-// cell's value. Columns are written last first, one byte per sequence
-// (0..3 a residue, 4 a gap).
+// Split, stage 2: one wave per box folds its chunks' results (same order:
+// larger value, then smaller index) into out[3b] = best, (p, q).
+__global__ void __launch_bounds__(64) k_split_final(const SplitDesc* __restrict__ boxes, uint32_t n,
+                                                    const int* __restrict__ partial,
+                                                    int* __restrict__ out) {
+  const uint32_t b = blockIdx.x;
+  if (b >= n) return;
+  const SplitDesc d = boxes[b];
+  int best = INT32_MIN;
+  uint32_t bidx = 0xFFFFFFFFu;
+  for (uint32_t c = threadIdx.x; c < d.nchunk; c += 64) {
+    const int v = partial[2 * (d.chunk0 + c)];
+    const uint32_t i = (uint32_t)partial[2 * (d.chunk0 + c) + 1];
+    if (v > best || (v == best && i < bidx)) {
+      best = v;
+      bidx = i;
+    }
+  }
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int v2 = __shfl_xor(best, m, 64);
+    const uint32_t i2 = (uint32_t)__shfl_xor((int)bidx, m, 64);
+    if (v2 > best || (v2 == best && i2 < bidx)) {
+      best = v2;
+      bidx = i2;
+    }
+  }
+  if (threadIdx.x == 0) {
+    out[3 * b] = best;
+    out[3 * b + 1] = (int)(bidx / d.cols);
+    out[3 * b + 2] = (int)(bidx % d.cols);
+  }
+}
+
+// One wave per leaf box: the table of Eq. 1 over the box (global
+// initialisation: the box's corner is 0, moves leaving the box do not exist)
+// in LDS, filled one anti-diagonal plane i + j + k = const at a time (every
+// predecessor lies on one of the three previous planes), then lane 0 walks
+// back from the far corner, taking at every cell the first move, in a fixed
+// order, whose predecessor plus column score gives the cell's value. Columns
+// are written last first, one byte per sequence (0..3 a residue, 4 a gap).
 __global__ void __launch_bounds__(64) k_leaf(LeafArgs a) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.n) return;
-  const LeafDesc d = a.leaves[t];
+  __shared__ int T[kLeafCells];
+  __shared__ uint8_t res[3][kLeafCells];
+  const uint32_t leaf = blockIdx.x;
+  if (leaf >= a.n) return;
+  const LeafDesc d = a.leaves[leaf];
   const int A = (int)d.len[0], B = (int)d.len[1], C = (int)d.len[2];
-  int* T = a.scratch + d.table;
+  const int lane = threadIdx.x;
+  for (int s = 0; s < 3; ++s)
+    for (int q = lane; q < (int)d.len[s]; q += 64) res[s][q] = (uint8_t)leaf_residue(a.words, d.off[s], d.lo[s] + q);
+  __syncthreads();
   const int sB = (B + 1) * (C + 1), sC = C + 1;
   const int g2 = 2 * a.gap;
   constexpr int kNone = INT32_MIN / 2;
-  for (int i = 0; i <= A; ++i) {
-    const int x = i ? (int)leaf_residue(a.words, d.off[0], d.lo[0] + i - 1) : 0;
-    for (int j = 0; j <= B; ++j) {
-      const int y = j ? (int)leaf_residue(a.words, d.off[1], d.lo[1] + j - 1) : 0;
-      for (int k = 0; k <= C; ++k) {
-        const int at = i * sB + j * sC + k;
-        if (i == 0 && j == 0 && k == 0) {
-          T[at] = 0;
-          continue;
-        }
-        const int z = k ? (int)leaf_residue(a.words, d.off[2], d.lo[2] + k - 1) : 0;
-        int m = kNone;
-        if (i && j && k) m = max(m, T[at - sB - sC - 1] + a.sub[4 * x + y] + a.sub[4 * x + z] + a.sub[4 * y + z]);
-        if (i && j) m = max(m, T[at - sB - sC] + a.sub[4 * x + y] + g2);
-        if (i && k) m = max(m, T[at - sB - 1] + a.sub[4 * x + z] + g2);
-        if (j && k) m = max(m, T[at - sC - 1] + a.sub[4 * y + z] + g2);
-        if (i) m = max(m, T[at - sB] + g2);
-        if (j) m = max(m, T[at - sC] + g2);
-        if (k) m = max(m, T[at - 1] + g2);
-        T[at] = m;
+  const int pairs = (A + 1) * (B + 1);
+  for (int dd = 0; dd <= A + B + C; ++dd) {
+    for (int q = lane; q < pairs; q += 64) {
+      const int i = q / (B + 1), j = q - i * (B + 1), k = dd - i - j;
+      if (k < 0 || k > C) continue;
+      const int at = i * sB + j * sC + k;
+      if (dd == 0) {
+        T[0] = 0;
+        continue;
       }
+      const int x = i ? res[0][i - 1] : 0, y = j ? res[1][j - 1] : 0, z = k ? res[2][k - 1] : 0;
+      int m = kNone;
+      if (i && j && k) m = max(m, T[at - sB - sC - 1] + a.sub[4 * x + y] + a.sub[4 * x + z] + a.sub[4 * y + z]);
+      if (i && j) m = max(m, T[at - sB - sC] + a.sub[4 * x + y] + g2);
+      if (i && k) m = max(m, T[at - sB - 1] + a.sub[4 * x + z] + g2);
+      if (j && k) m = max(m, T[at - sC - 1] + a.sub[4 * y + z] + g2);
+      if (i) m = max(m, T[at - sB] + g2);
+      if (j) m = max(m, T[at - sC] + g2);
+      if (k) m = max(m, T[at - 1] + g2);
+      T[at] = m;
     }
+    __syncthreads();
   }
-  a.score[t] = T[A * sB + B * sC + C];
+  if (lane != 0) return;
+  a.score[leaf] = T[A * sB + B * sC + C];
   uint8_t* out = a.cols + d.out;
   int i = A, j = B, k = C, n = 0;
   while (i || j || k) {
     const int at = i * sB + j * sC + k;
     const int v = T[at];
-    const int x = i ? (int)leaf_residue(a.words, d.off[0], d.lo[0] + i - 1) : 0;
-    const int y = j ? (int)leaf_residue(a.words, d.off[1], d.lo[1] + j - 1) : 0;
-    const int z = k ? (int)leaf_residue(a.words, d.off[2], d.lo[2] + k - 1) : 0;
+    const int x = i ? res[0][i - 1] : 0, y = j ? res[1][j - 1] : 0, z = k ? res[2][k - 1] : 0;
     int di = 0, dj = 0, dk = 0;
     if (i && j && k && T[at - sB - sC - 1] + a.sub[4 * x + y] + a.sub[4 * x + z] + a.sub[4 * y + z] == v) {
       di = dj = dk = 1;
@@ -137,20 +177,23 @@ __global__ void __launch_bounds__(64) k_leaf(LeafArgs a) {
     j -= dj;
     k -= dk;
   }
-  a.ncols[t] = (uint32_t)n;
+  a.ncols[leaf] = (uint32_t)n;
 }
 
 }  // namespace
 
-hipError_t launch_split(const int* planes, const SplitDesc* boxes, uint32_t n, int* out, hipStream_t s) {
+hipError_t launch_split(const int* planes, const SplitDesc* boxes, uint32_t n, const uint32_t* chunk_box,
+                        uint32_t nchunks, int* partial, int* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_split, dim3(n), dim3(256), 0, s, planes, boxes, n, out);
+  hipLaunchKernelGGL(k_split_part, dim3(nchunks), dim3(256), 0, s, planes, boxes, chunk_box, nchunks,
+                     partial);
+  hipLaunchKernelGGL(k_split_final, dim3(n), dim3(64), 0, s, boxes, n, partial, out);
   return hipGetLastError();
 }
 
 hipError_t launch_leaf(const LeafArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_leaf, dim3((a.n + 63) / 64), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_leaf, dim3(a.n), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
