@@ -20,9 +20,10 @@
  *  - Lengths may be 0. A triplet's cell count is a*b*c (the paper's TCUPS
  *    definition, Section V-A).
  *  - Every call returns a trioseq_status; on error the outputs are left
- *    untouched, no kernel has been launched, and trioseq_last_error() returns
- *    a message for the calling thread. Batch validation is all-or-nothing and
- *    the message names the first bad triplet.
+ *    untouched and trioseq_last_error() returns a message for the calling
+ *    thread. Inputs are validated before any kernel is launched (a
+ *    validation error launches nothing); batch validation is all-or-nothing
+ *    and the message names the first bad triplet.
  *  - No C++ exception crosses this ABI.
  *  - "hip_stream" arguments take a hipStream_t (NULL = the null stream).
  */

@@ -309,7 +309,7 @@ trioseq_status align_batch_impl(const trioseq_triplet* t, size_t n, const triose
 
 using namespace trioseq;
 
-extern "C" trioseq_status trioseq_align_batch(const trioseq_triplet* t, size_t n,
+static trioseq_status trioseq_align_batch_body(const trioseq_triplet* t, size_t n,
                                               const trioseq_scoring* sc, char* rows, uint32_t* ncols,
                                               int32_t* scores, void* hip_stream) {
   if (!sc || (n && (!t || !rows || !ncols || !scores)))
@@ -320,7 +320,7 @@ extern "C" trioseq_status trioseq_align_batch(const trioseq_triplet* t, size_t n
   return align_batch_impl(t, n, *sc, rows, ncols, scores, (hipStream_t)hip_stream);
 }
 
-extern "C" trioseq_status trioseq_align(const trioseq_triplet* t, const trioseq_scoring* sc,
+static trioseq_status trioseq_align_body(const trioseq_triplet* t, const trioseq_scoring* sc,
                                         char* row0, char* row1, char* row2, uint32_t cap,
                                         uint32_t* ncols, int32_t* score, void* hip_stream) {
   if (!t || !sc || !row0 || !row1 || !row2 || !ncols || !score)
@@ -342,3 +342,16 @@ extern "C" trioseq_status trioseq_align(const trioseq_triplet* t, const trioseq_
   *score = sco;
   return TRIOSEQ_OK;
 }
+
+// Entry points: every body runs guarded (no exception crosses the ABI).
+extern "C" {
+
+trioseq_status trioseq_align_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc, char* rows, uint32_t* ncols, int32_t* scores, void* hip_stream) {
+  return guarded([&] { return trioseq_align_batch_body(t, n, sc, rows, ncols, scores, hip_stream); });
+}
+
+trioseq_status trioseq_align(const trioseq_triplet* t, const trioseq_scoring* sc, char* row0, char* row1, char* row2, uint32_t cap, uint32_t* ncols, int32_t* score, void* hip_stream) {
+  return guarded([&] { return trioseq_align_body(t, sc, row0, row1, row2, cap, ncols, score, hip_stream); });
+}
+
+}  // extern "C"

@@ -635,7 +635,7 @@ const int* plan_planes(const trioseq_plan* p) { return p->d_plane; }
 
 extern "C" {
 
-trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_off, size_t n,
+static trioseq_status trioseq_plan_create_body(const uint32_t* lens, const uint64_t* word_off, size_t n,
                                    const trioseq_scoring* scp, const trioseq_plan_options* opts,
                                    trioseq_plan** out) {
   return plan_create_impl(lens, word_off, n, scp, opts, false, nullptr, 0, out);
@@ -766,7 +766,7 @@ static trioseq_status run_host_batch(const trioseq_triplet* t, size_t n, const t
   return TRIOSEQ_OK;
 }
 
-trioseq_status trioseq_autotune(const uint32_t* lens, const uint64_t* word_off, size_t n,
+static trioseq_status trioseq_autotune_body(const uint32_t* lens, const uint64_t* word_off, size_t n,
                                 const trioseq_scoring* sc, const uint32_t* d_words, int32_t reps,
                                 void* hip_stream, trioseq_tune_result* out) {
   if (!out || !sc || (n && (!lens || !d_words)))
@@ -851,14 +851,35 @@ trioseq_status trioseq_autotune(const uint32_t* lens, const uint64_t* word_off, 
   return TRIOSEQ_OK;
 }
 
-trioseq_status trioseq_score(const trioseq_triplet* t, const trioseq_scoring* sc, int32_t* score) {
+static trioseq_status trioseq_score_body(const trioseq_triplet* t, const trioseq_scoring* sc, int32_t* score) {
   if (!t || !score) return fail(TRIOSEQ_ERR_INVALID_ARG, "score: NULL pointer");
   return run_host_batch(t, 1, sc, score, nullptr, -1);
 }
 
-trioseq_status trioseq_score_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
+static trioseq_status trioseq_score_batch_body(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
                                    int32_t* scores, void* hip_stream) {
   return run_host_batch(t, n, sc, scores, (hipStream_t)hip_stream, -1);
+}
+
+}  // extern "C"
+
+// Entry points: every body runs guarded (no exception crosses the ABI).
+extern "C" {
+
+trioseq_status trioseq_plan_create(const uint32_t* lens, const uint64_t* word_off, size_t n, const trioseq_scoring* scp, const trioseq_plan_options* opts, trioseq_plan** out) {
+  return guarded([&] { return trioseq_plan_create_body(lens, word_off, n, scp, opts, out); });
+}
+
+trioseq_status trioseq_autotune(const uint32_t* lens, const uint64_t* word_off, size_t n, const trioseq_scoring* sc, const uint32_t* d_words, int32_t reps, void* hip_stream, trioseq_tune_result* out) {
+  return guarded([&] { return trioseq_autotune_body(lens, word_off, n, sc, d_words, reps, hip_stream, out); });
+}
+
+trioseq_status trioseq_score(const trioseq_triplet* t, const trioseq_scoring* sc, int32_t* score) {
+  return guarded([&] { return trioseq_score_body(t, sc, score); });
+}
+
+trioseq_status trioseq_score_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc, int32_t* scores, void* hip_stream) {
+  return guarded([&] { return trioseq_score_batch_body(t, n, sc, scores, hip_stream); });
 }
 
 }  // extern "C"

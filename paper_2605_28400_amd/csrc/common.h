@@ -2,6 +2,7 @@
 #pragma once
 #include <stdint.h>
 
+#include <new>
 #include <string>
 #include <vector>
 
@@ -11,6 +12,20 @@
 namespace trioseq {
 
 trioseq_status fail(trioseq_status st, const std::string& msg);
+
+// Runs an entry point's body so that no C++ exception leaves the C ABI:
+// a failed host allocation becomes TRIOSEQ_ERR_NOMEM, anything else
+// TRIOSEQ_ERR_DEVICE.
+template <class F>
+trioseq_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(TRIOSEQ_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(TRIOSEQ_ERR_DEVICE, "unexpected host exception");
+  }
+}
 trioseq_status fail_hip(hipError_t e, const char* what);
 #define TRIOSEQ_HIP(call, what)                              \
   do {                                                       \

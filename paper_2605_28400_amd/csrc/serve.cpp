@@ -325,7 +325,7 @@ void free_server(trioseq_server* s) {
 
 extern "C" {
 
-trioseq_status trioseq_serve_create(const trioseq_serve_config* cfg, const trioseq_scoring* sc,
+static trioseq_status trioseq_serve_create_body(const trioseq_serve_config* cfg, const trioseq_scoring* sc,
                                     trioseq_server** out) {
   if (!cfg || !sc || !out) return fail(TRIOSEQ_ERR_INVALID_ARG, "serve_create: NULL pointer");
   trioseq_status st = validate_scoring(sc);
@@ -427,7 +427,7 @@ trioseq_status trioseq_serve_create(const trioseq_serve_config* cfg, const trios
   return TRIOSEQ_OK;
 }
 
-trioseq_status trioseq_serve_submit(trioseq_server* s, const trioseq_triplet* t, uint64_t* id) {
+static trioseq_status trioseq_serve_submit_body(trioseq_server* s, const trioseq_triplet* t, uint64_t* id) {
   if (!s || !t || !id) return fail(TRIOSEQ_ERR_INVALID_ARG, "serve_submit: NULL pointer");
   Request r;
   uint64_t words = 0;
@@ -460,7 +460,7 @@ trioseq_status trioseq_serve_submit(trioseq_server* s, const trioseq_triplet* t,
   return TRIOSEQ_OK;
 }
 
-trioseq_status trioseq_serve_poll(trioseq_server* s, trioseq_result* out, size_t cap, size_t* n_out) {
+static trioseq_status trioseq_serve_poll_body(trioseq_server* s, trioseq_result* out, size_t cap, size_t* n_out) {
   if (!s || !n_out || (cap && !out)) return fail(TRIOSEQ_ERR_INVALID_ARG, "serve_poll: NULL pointer");
   std::lock_guard<std::mutex> lk(s->mu);
   size_t k = 0;
@@ -477,7 +477,7 @@ trioseq_status trioseq_serve_poll(trioseq_server* s, trioseq_result* out, size_t
   return TRIOSEQ_OK;
 }
 
-trioseq_status trioseq_serve_wait(trioseq_server* s, uint64_t id, trioseq_result* out,
+static trioseq_status trioseq_serve_wait_body(trioseq_server* s, uint64_t id, trioseq_result* out,
                                   int64_t timeout_ns) {
   if (!s || !out) return fail(TRIOSEQ_ERR_INVALID_ARG, "serve_wait: NULL pointer");
   std::unique_lock<std::mutex> lk(s->mu);
@@ -495,7 +495,7 @@ trioseq_status trioseq_serve_wait(trioseq_server* s, uint64_t id, trioseq_result
   return TRIOSEQ_OK;
 }
 
-trioseq_status trioseq_serve_get_stats(trioseq_server* s, trioseq_serve_stats* st) {
+static trioseq_status trioseq_serve_get_stats_body(trioseq_server* s, trioseq_serve_stats* st) {
   if (!s || !st) return fail(TRIOSEQ_ERR_INVALID_ARG, "serve_get_stats: NULL pointer");
   std::vector<double> lat;
   {
@@ -532,6 +532,31 @@ trioseq_status trioseq_serve_destroy(trioseq_server* s) {
   (void)hipDeviceSynchronize();
   free_server(s);
   return TRIOSEQ_OK;
+}
+
+}  // extern "C"
+
+// Entry points: every body runs guarded (no exception crosses the ABI).
+extern "C" {
+
+trioseq_status trioseq_serve_create(const trioseq_serve_config* cfg, const trioseq_scoring* sc, trioseq_server** out) {
+  return guarded([&] { return trioseq_serve_create_body(cfg, sc, out); });
+}
+
+trioseq_status trioseq_serve_submit(trioseq_server* s, const trioseq_triplet* t, uint64_t* id) {
+  return guarded([&] { return trioseq_serve_submit_body(s, t, id); });
+}
+
+trioseq_status trioseq_serve_poll(trioseq_server* s, trioseq_result* out, size_t cap, size_t* n_out) {
+  return guarded([&] { return trioseq_serve_poll_body(s, out, cap, n_out); });
+}
+
+trioseq_status trioseq_serve_wait(trioseq_server* s, uint64_t id, trioseq_result* out, int64_t timeout_ns) {
+  return guarded([&] { return trioseq_serve_wait_body(s, id, out, timeout_ns); });
+}
+
+trioseq_status trioseq_serve_get_stats(trioseq_server* s, trioseq_serve_stats* st) {
+  return guarded([&] { return trioseq_serve_get_stats_body(s, st); });
 }
 
 }  // extern "C"
