@@ -104,6 +104,20 @@ trioseq_status trioseq_score(const trioseq_triplet* t, const trioseq_scoring* sc
 trioseq_status trioseq_score_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
                                    int32_t* scores, void* hip_stream);
 
+/* Scores of n triplets whose packed residues are already in device memory
+ * (e.g. torch-owned buffers). d_words: packed residues (trioseq_pack layout);
+ * d_word_off / d_len: 3n entries each in device memory, sequence s of triplet
+ * t starting at word d_word_off[3t+s] with d_len[3t+s] residues; d_scores: n
+ * int32 in device memory. The offsets and lengths are read back first (the
+ * call waits for hip_stream to reach it); the batch is then laid out, or the
+ * layout of this thread's previous call is reused when lengths, offsets,
+ * scoring and device are unchanged, and the scoring is enqueued on hip_stream
+ * without waiting for it: d_words and d_scores must stay alive until the
+ * stream passes this point. */
+trioseq_status trioseq_score_batch_packed(const uint32_t* d_words, const uint64_t* d_word_off,
+                                          const uint32_t* d_len, size_t n, const trioseq_scoring* sc,
+                                          int32_t* d_scores, void* hip_stream);
+
 /* Optimal global alignment of one triplet: the traceback (Section II, Eq. 1
  * for the scores; the alignment is recovered in linear space by Hirschberg's
  * divide and conquer, which the paper names for its traceback). row0, row1,

@@ -81,7 +81,7 @@ class ServeStats(ctypes.Structure):
 # Every symbol the C header declares (checked by the CPU test-suite).
 EXPORTS = [
     "trioseq_scoring_simple", "trioseq_pack", "trioseq_packed_layout", "trioseq_score",
-    "trioseq_score_batch", "trioseq_plan_create", "trioseq_plan_run", "trioseq_plan_get_info",
+    "trioseq_score_batch", "trioseq_score_batch_packed", "trioseq_plan_create", "trioseq_plan_run", "trioseq_plan_get_info",
     "trioseq_plan_destroy", "trioseq_autotune", "trioseq_align", "trioseq_align_batch", "trioseq_serve_create", "trioseq_serve_submit", "trioseq_serve_poll",
     "trioseq_serve_wait", "trioseq_serve_get_stats", "trioseq_serve_destroy",
     "trioseq_last_error", "trioseq_version",
@@ -137,6 +137,10 @@ def lib() -> ctypes.CDLL:
     L.trioseq_serve_get_stats.restype = st
     L.trioseq_serve_destroy.argtypes = [ctypes.c_void_p]
     L.trioseq_serve_destroy.restype = st
+    L.trioseq_score_batch_packed.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_size_t, P(Scoring), ctypes.c_void_p,
+                                             ctypes.c_void_p]
+    L.trioseq_score_batch_packed.restype = st
     L.trioseq_align.argtypes = [P(Triplet), P(Scoring), ctypes.c_char_p, ctypes.c_char_p,
                                 ctypes.c_char_p, ctypes.c_uint32, P(ctypes.c_uint32),
                                 P(ctypes.c_int32), ctypes.c_void_p]
@@ -209,6 +213,21 @@ def score(triplet, sc: Scoring | None = None) -> int:
     out = ctypes.c_int32()
     check(lib().trioseq_score(ctypes.byref(tr), ctypes.byref(sc or _default_scoring()), ctypes.byref(out)))
     return int(out.value)
+
+
+def score_batch_packed(d_words, d_word_off, d_len, d_scores, n: int, sc: Scoring | None = None,
+                       stream=None) -> None:
+    """Scores of n triplets already in device memory (torch tensors or raw
+    pointers): d_word_off (3n uint64), d_len (3n uint32), d_scores (n int32).
+    Enqueued on ``stream`` (torch's current stream by default)."""
+    ptr = lambda b: b.data_ptr() if hasattr(b, "data_ptr") else int(b)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    check(lib().trioseq_score_batch_packed(ctypes.c_void_p(ptr(d_words)), ctypes.c_void_p(ptr(d_word_off)),
+                                           ctypes.c_void_p(ptr(d_len)), n,
+                                           ctypes.byref(sc or _default_scoring()),
+                                           ctypes.c_void_p(ptr(d_scores)), _stream_ptr(stream)))
 
 
 def align(triplet, sc: Scoring | None = None, stream=None):

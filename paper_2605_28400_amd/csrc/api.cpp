@@ -732,6 +732,64 @@ static trioseq_status pack_triplets(const trioseq_triplet* t, size_t n, std::vec
   return TRIOSEQ_OK;
 }
 
+// trioseq_score_batch_packed: this thread's last plan, reused while the
+// batch (lengths, word offsets, scoring, device) stays the same. It is never
+// freed at thread exit (the HIP runtime may already be gone then).
+struct PackedCache {
+  std::vector<uint32_t> lens;
+  std::vector<uint64_t> offs;
+  trioseq_scoring sc{};
+  int device = -1;
+  trioseq_plan* plan = nullptr;
+  hipStream_t stream = nullptr;  // where the plan last ran
+};
+static thread_local PackedCache* g_packed = nullptr;
+
+static trioseq_status score_batch_packed_body(const uint32_t* d_words, const uint64_t* d_word_off,
+                                              const uint32_t* d_len, size_t n, const trioseq_scoring* sc,
+                                              int32_t* d_scores, void* hip_stream) {
+  if (!sc) return fail(TRIOSEQ_ERR_INVALID_ARG, "score_batch_packed: scoring is NULL");
+  if (n && (!d_words || !d_word_off || !d_len || !d_scores))
+    return fail(TRIOSEQ_ERR_INVALID_ARG, "score_batch_packed: NULL device buffer");
+  trioseq_status st = validate_scoring(sc);
+  if (st != TRIOSEQ_OK) return st;
+  if (n == 0) return TRIOSEQ_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<uint32_t> lens(3 * n);
+  std::vector<uint64_t> offs(3 * n);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(lens.data(), d_len, 3 * n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(offs.data(), d_word_off, 3 * n * 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return fail_hip(e, "score_batch_packed: reading lengths");
+  int device = 0;
+  TRIOSEQ_HIP(hipGetDevice(&device), "hipGetDevice");
+  if (!g_packed) g_packed = new PackedCache;
+  PackedCache& c = *g_packed;
+  const bool same = c.plan && c.device == device && c.lens == lens && c.offs == offs &&
+                    std::memcmp(&c.sc, sc, sizeof *sc) == 0;
+  if (!same) {
+    trioseq_plan* plan = nullptr;
+    st = trioseq_plan_create(lens.data(), offs.data(), n, sc, nullptr, &plan);
+    if (st != TRIOSEQ_OK) return st;
+    if (c.plan) {
+      // The old plan's workspace may still be in use on the stream it ran on.
+      (void)hipStreamSynchronize(c.stream);
+      trioseq_plan_destroy(c.plan);
+    }
+    c.plan = plan;
+    c.lens.swap(lens);
+    c.offs.swap(offs);
+    c.sc = *sc;
+    c.device = device;
+  }
+  // Runs of one plan share its workspace: a run on another stream waits for
+  // the previous one.
+  if (c.stream != s) (void)hipStreamSynchronize(c.stream);
+  c.stream = s;
+  return trioseq_plan_run(c.plan, d_words, d_scores, hip_stream);
+}
+
 static trioseq_status run_host_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
                                      int32_t* scores, hipStream_t s, int engine) {
   if (n && !scores) return fail(TRIOSEQ_ERR_INVALID_ARG, "scores is NULL");
@@ -876,6 +934,14 @@ trioseq_status trioseq_autotune(const uint32_t* lens, const uint64_t* word_off, 
 
 trioseq_status trioseq_score(const trioseq_triplet* t, const trioseq_scoring* sc, int32_t* score) {
   return guarded([&] { return trioseq_score_body(t, sc, score); });
+}
+
+trioseq_status trioseq_score_batch_packed(const uint32_t* d_words, const uint64_t* d_word_off,
+                                          const uint32_t* d_len, size_t n, const trioseq_scoring* sc,
+                                          int32_t* d_scores, void* hip_stream) {
+  return guarded([&] {
+    return score_batch_packed_body(d_words, d_word_off, d_len, n, sc, d_scores, hip_stream);
+  });
 }
 
 trioseq_status trioseq_score_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc, int32_t* scores, void* hip_stream) {

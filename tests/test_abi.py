@@ -165,3 +165,10 @@ def test_align_batch_rejects_bad_input():
     assert L.trioseq_align_batch(arr, 1, ctypes.byref(ts.scoring(kind=ts.SEMI_GLOBAL)), buf,
                                  ctypes.byref(n), ctypes.byref(s), None) == -1
     assert ts.align_batch([]) == []
+
+
+def test_score_batch_packed_rejects_bad_input():
+    L = ts.lib()
+    assert L.trioseq_score_batch_packed(None, None, None, 3, ctypes.byref(ts.scoring()), None, None) == -1
+    assert L.trioseq_score_batch_packed(None, None, None, 3, None, None, None) == -1
+    assert L.trioseq_score_batch_packed(None, None, None, 0, ctypes.byref(ts.scoring()), None, None) == 0
