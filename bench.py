@@ -80,6 +80,20 @@ def parse():
     return ap.parse_args()
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and logical CPU count (reported beside the oracle)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
 def cpu_baseline(workload, budget_s: float = 20.0, kind: str = "global"):
     """The oracle, as is, on a bounded sample of the workload (host cores)."""
     import oracle
@@ -102,7 +116,7 @@ def cpu_baseline(workload, budget_s: float = 20.0, kind: str = "global"):
         score = oracle.score(t, kind=okind)
         dt = time.perf_counter() - t0
         return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": cores, "kind": "oracle",
-                "sample": sample, "seconds": round(dt, 3)}, score
+                "sample": sample, "seconds": round(dt, 3), **host_cpu()}, score
     # Batched: as many triplets (in workload order) as fit the time budget
     # at the oracle's measured rate, on all host cores.
     probe = trips[:cores]
@@ -122,7 +136,7 @@ def cpu_baseline(workload, budget_s: float = 20.0, kind: str = "global"):
     dt = time.perf_counter() - t0
     return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": cores, "kind": "oracle",
             "sample": f"first {take} of {len(trips)} triplets on {cores} threads",
-            "seconds": round(dt, 3)}, None
+            "seconds": round(dt, 3), **host_cpu()}, None
 
 
 def per_triplet(ts, torch, trips, sample: int, stream, ref_scores=None, spread: bool = False,
@@ -395,6 +409,9 @@ def main():
                      "frac": round(achieved / PEAK_INT32_TOPS, 4),
                      "traffic": measured_traffic(workload.name) if args.kind == "global" else None,
                      "kernel_ms": round(ms_events, 4), "ops_per_cell": ops,
+                     # Eq. 1 counted as 7 sums and a 7-way maximum (13 two-input operations).
+                     "frac_13_ops_per_cell": round(cells * (ops + 6) / (ms_events * 1e-3) / 1e12
+                                                   / PEAK_INT32_TOPS, 4),
                      "kernel": ["k_sweep (persistent job queue, whole-triplet jobs)",
                                 "k_panel (persistent job queue, two-wave panel workgroups)",
                                 "k_sweep (persistent job queue, whole-triplet and panel jobs)"][info["engine"]]},
