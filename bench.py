@@ -38,16 +38,21 @@ WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served", "tr
 # WRITE_SIZE runs scaled by the same counters on a plain 1 GiB copy (summaries
 # with the commands are under profiles/). Each figure holds only for the kernel
 # source it was measured on; for any other source the field is null.
+# Keyed by (workload, kind, lane tile): the autotuner may pick another tile.
 TRAFFIC = {
-    "single_1024x1000x1048": (1.5689e9, "5b986628d09c52c4"),
-    "batch_8192_len100-400": (7.2410e10, "5b986628d09c52c4"),
-    "single_4096x4000x4150": (7.9174e10, "5b986628d09c52c4"),
+    ("single_1024x1000x1048", "global", "4x4"): (1.5689e9, "5b986628d09c52c4"),
+    ("batch_8192_len100-400", "global", "8x4"): (7.2410e10, "5b986628d09c52c4"),
+    ("single_4096x4000x4150", "global", "4x4"): (7.9174e10, "5b986628d09c52c4"),
+    ("single_1024x1000x1048", "local", "4x4"): (1.6522e9, "5b986628d09c52c4"),
+    ("batch_8192_len100-400", "local", "4x4"): (9.7230e10, "5b986628d09c52c4"),
+    ("single_1024x1000x1048", "semi-global", "4x4"): (1.6210e9, "5b986628d09c52c4"),
+    ("batch_8192_len100-400", "semi-global", "8x4"): (7.3193e10, "5b986628d09c52c4"),
 }
 
 
-def measured_traffic(workload_name: str):
+def measured_traffic(workload_name: str, kind: str, tile: str):
     import hashlib
-    entry = TRAFFIC.get(workload_name)
+    entry = TRAFFIC.get((workload_name, kind, tile))
     if entry is None:
         return None
     src = os.path.join(ROOT, "paper_2605_28400_amd", "csrc", "sweep.hip")
@@ -407,7 +412,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOP/s",
                      "frac": round(achieved / PEAK_INT32_TOPS, 4),
-                     "traffic": measured_traffic(workload.name) if args.kind == "global" else None,
+                     "traffic": measured_traffic(workload.name, args.kind,
+                                                 f"{info['tile_rows']}x{info['tile_cols']}"),
                      "kernel_ms": round(ms_events, 4), "ops_per_cell": ops,
                      # Eq. 1 counted as 7 sums and a 7-way maximum (13 two-input operations).
                      "frac_13_ops_per_cell": round(cells * (ops + 6) / (ms_events * 1e-3) / 1e12
