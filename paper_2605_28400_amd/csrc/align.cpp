@@ -58,9 +58,10 @@ constexpr size_t kLeavesPerLaunch = 1 << 18;
 
 // One level: every box in `boxes` is split; its two children go to `next`.
 // root_score[t] is set when the box is triplet t's root (its first split).
-trioseq_status split_level(const std::vector<Box>& boxes, const std::vector<std::vector<uint8_t>>& codes,
-                           const trioseq_scoring& sc, std::vector<char>& split_seen,
-                           std::vector<int32_t>& root_score, std::vector<Box>& next, hipStream_t s) {
+trioseq_status split_level(PlaneWorkspace& ws, const std::vector<Box>& boxes,
+                           const std::vector<std::vector<uint8_t>>& codes, const trioseq_scoring& sc,
+                           std::vector<char>& split_seen, std::vector<int32_t>& root_score,
+                           std::vector<Box>& next, hipStream_t s) {
   const size_t nb = boxes.size();
   // Triplet 2q = first half of box q forward, 2q + 1 = second half reversed;
   // the halved axis is swept, the other two stay in index order.
@@ -102,35 +103,25 @@ trioseq_status split_level(const std::vector<Box>& boxes, const std::vector<std:
     sd[q] = SplitDesc{poff[2 * q], poff[2 * q + 1], prow, pcol, (uint32_t)chunk_box.size(), nchunk};
     chunk_box.insert(chunk_box.end(), nchunk, (uint32_t)q);
   }
-  trioseq_plan* plan = nullptr;
-  trioseq_status st = plan_create_planes(lens.data(), offs.data(), 2 * nb, sc, poff.data(), pints, &plan);
+  trioseq_status st = run_planes(ws, lens.data(), offs.data(), 2 * nb, words.data(), words.size(), sc,
+                                 poff.data(), pints, s);
   if (st != TRIOSEQ_OK) return st;
-  DevBuf d_words, d_scores, d_sd, d_out, d_chunk_box, d_partial;
+  DevBuf d_sd, d_out, d_chunk_box, d_partial;
   std::vector<int> out(3 * nb);
   const size_t nchunks = chunk_box.size();
   hipError_t e;
-  if ((e = d_words.alloc(words.size() * 4)) != hipSuccess || (e = d_scores.alloc(2 * nb * 4)) != hipSuccess ||
-      (e = d_sd.alloc(nb * sizeof(SplitDesc))) != hipSuccess || (e = d_out.alloc(3 * nb * 4)) != hipSuccess ||
+  if ((e = d_sd.alloc(nb * sizeof(SplitDesc))) != hipSuccess || (e = d_out.alloc(3 * nb * 4)) != hipSuccess ||
       (e = d_chunk_box.alloc(nchunks * 4)) != hipSuccess || (e = d_partial.alloc(nchunks * 8)) != hipSuccess ||
-      (e = hipMemcpyAsync(d_words.p, words.data(), words.size() * 4, hipMemcpyHostToDevice, s)) !=
-          hipSuccess ||
       (e = hipMemcpyAsync(d_sd.p, sd.data(), nb * sizeof(SplitDesc), hipMemcpyHostToDevice, s)) !=
           hipSuccess ||
       (e = hipMemcpyAsync(d_chunk_box.p, chunk_box.data(), nchunks * 4, hipMemcpyHostToDevice, s)) !=
-          hipSuccess) {
-    trioseq_plan_destroy(plan);
-    return hip_err(e, "align: plane batch");
-  }
-  st = trioseq_plan_run(plan, d_words.as<uint32_t>(), d_scores.as<int32_t>(), s);
-  if (st == TRIOSEQ_OK) {
-    e = launch_split(plan_planes(plan), d_sd.as<SplitDesc>(), (uint32_t)nb, d_chunk_box.as<uint32_t>(),
-                     (uint32_t)nchunks, d_partial.as<int>(), d_out.as<int>(), s);
-    if (e == hipSuccess) e = hipMemcpyAsync(out.data(), d_out.p, 3 * nb * 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) st = hip_err(e, "align: split");
-  }
-  trioseq_plan_destroy(plan);
-  if (st != TRIOSEQ_OK) return st;
+          hipSuccess ||
+      (e = launch_split((const int*)ws.plane.p, d_sd.as<SplitDesc>(), (uint32_t)nb,
+                        d_chunk_box.as<uint32_t>(), (uint32_t)nchunks, d_partial.as<int>(),
+                        d_out.as<int>(), s)) != hipSuccess ||
+      (e = hipMemcpyAsync(out.data(), d_out.p, 3 * nb * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_err(e, "align: split");
   for (size_t q = 0; q < nb; ++q) {
     const Box& b = boxes[q];
     const int ax = axes[3 * q], r = axes[3 * q + 1], c = axes[3 * q + 2];
@@ -237,11 +228,12 @@ trioseq_status align_batch_impl(const trioseq_triplet* t, size_t n, const triose
   for (size_t u = 0; u < n; ++u) work.push_back(Box{(uint32_t)u, {0, 0, 0}, {t[u].len[0], t[u].len[1], t[u].len[2]}});
   std::vector<char> split_seen(n, 0);
   std::vector<int32_t> root_score(n, 0);
+  PlaneWorkspace ws;
   while (!work.empty()) {
     std::vector<Box> boxes, next;
     for (const Box& b : work) (b.cells() <= kLeafCells ? leaves : boxes).push_back(b);
     if (boxes.empty()) break;
-    trioseq_status st = split_level(boxes, codes, sc, split_seen, root_score, next, s);
+    trioseq_status st = split_level(ws, boxes, codes, sc, split_seen, root_score, next, s);
     if (st != TRIOSEQ_OK) return st;
     work.swap(next);
   }

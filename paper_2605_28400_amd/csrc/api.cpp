@@ -236,8 +236,6 @@ struct trioseq_plan {
   Boundary bnd{};
   int* d_red = nullptr;      // per-triplet reduction pairs (semi-global, local)
   uint32_t red_pairs = 0;
-  int* d_plane = nullptr;          // last-slice planes (traceback plans only)
-  uint64_t* d_plane_off = nullptr;
   // graph replay
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
@@ -260,8 +258,6 @@ static void plan_free(trioseq_plan* p) {
   (void)hipFree(p->d_pface);
   (void)hipFree(p->d_bnd);
   (void)hipFree(p->d_red);
-  (void)hipFree(p->d_plane);
-  (void)hipFree(p->d_plane_off);
   delete p;
 }
 
@@ -511,31 +507,26 @@ trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested
 
 }  // namespace trioseq
 
-// Plans, with or without last-slice planes (traceback): planes = the run
-// also writes triplet t's last slice to the plan's plane buffer at
-// plane_off[t] (plane_ints ints in all).
 static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* word_off, size_t n,
                                        const trioseq_scoring* scp, const trioseq_plan_options* opts,
-                                       bool planes, const uint64_t* plane_off, uint64_t plane_ints,
                                        trioseq_plan** out) {
   if (!out) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: plan output is NULL");
   if (!scp) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: scoring is NULL");
   trioseq_plan_options o{-1, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
-  if (planes) o = trioseq_plan_options{-1, 4, 4, 0, 0, 2};  // the plane kernels' shape
   if (!o.tile_rows && !o.tile_cols && !o.waves_per_simd && lens) apply_tuned(lens, n, scp->kind, &o);
   // Inputs are validated (by the layout) before the device is touched; the
   // layout is redone if the device's size changes the split rule's hint.
   Layout L;
   int hint = 256 * kWavesPerCuHint;
-  trioseq_status st = build_layout(lens, word_off, n, *scp, o, hint, &L, planes);
+  trioseq_status st = build_layout(lens, word_off, n, *scp, o, hint, &L);
   if (st != TRIOSEQ_OK) return st;
   DeviceProps dp;
   st = device_props(&dp);
   if (st != TRIOSEQ_OK) return st;
   if (dp.cus * kWavesPerCuHint != hint) {
     hint = dp.cus * kWavesPerCuHint;
-    st = build_layout(lens, word_off, n, *scp, o, hint, &L, planes);
+    st = build_layout(lens, word_off, n, *scp, o, hint, &L);
     if (st != TRIOSEQ_OK) return st;
   }
 
@@ -590,16 +581,6 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
       return hip_bail(e, "hipMalloc panel faces");
     if ((e = hipMemset(p->d_pface, 0, pool_bytes)) != hipSuccess) return hip_bail(e, "hipMemset");
   }
-  if (planes && n) {
-    if ((e = hipMalloc((void**)&p->d_plane, std::max<uint64_t>(plane_ints, 1) * sizeof(int))) !=
-        hipSuccess)
-      return hip_bail(e, "hipMalloc planes");
-    if ((e = hipMalloc((void**)&p->d_plane_off, n * sizeof(uint64_t))) != hipSuccess)
-      return hip_bail(e, "hipMalloc plane offsets");
-    if ((e = hipMemcpy(p->d_plane_off, plane_off, n * sizeof(uint64_t), hipMemcpyHostToDevice)) !=
-        hipSuccess)
-      return hip_bail(e, "hipMemcpy plane offsets");
-  }
   p->red_pairs = L.red_pairs();
   if (p->red_pairs &&
       (e = hipMalloc((void**)&p->d_red, (uint64_t)p->red_pairs * 2 * sizeof(int))) != hipSuccess)
@@ -623,13 +604,92 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
 
 namespace trioseq {
 
-trioseq_status plan_create_planes(const uint32_t* lens, const uint64_t* off, size_t n,
-                                  const trioseq_scoring& sc, const uint64_t* plane_off,
-                                  uint64_t plane_ints, trioseq_plan** out) {
-  return plan_create_impl(lens, off, n, &sc, nullptr, true, plane_off, plane_ints, out);
+PlaneWorkspace::~PlaneWorkspace() {
+  for (Buf* b : {&ctl, &desc, &jobs, &face, &pool, &bnd, &red, &plane, &plane_off, &words, &scores})
+    (void)hipFree(b->p);
 }
 
-const int* plan_planes(const trioseq_plan* p) { return p->d_plane; }
+// Makes b hold at least `bytes` (contents not kept). zero: clear a new buffer.
+static hipError_t ws_grow(PlaneWorkspace::Buf& b, uint64_t bytes, bool zero, hipStream_t s) {
+  bytes = std::max<uint64_t>(bytes, 256);
+  if (b.bytes >= bytes) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(s);  // the old buffer may still be in use
+  if (e != hipSuccess) return e;
+  (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+  const uint64_t cap = bytes + bytes / 4;  // room for the next, similar run
+  if ((e = hipMalloc(&b.p, cap)) != hipSuccess) return e;
+  b.bytes = cap;
+  if (zero) e = hipMemsetAsync(b.p, 0, cap, s);
+  return e;
+}
+
+trioseq_status run_planes(PlaneWorkspace& ws, const uint32_t* lens, const uint64_t* offs, size_t n,
+                          const uint32_t* words, size_t nwords, const trioseq_scoring& sc,
+                          const uint64_t* plane_off, uint64_t plane_ints, hipStream_t s) {
+  if (n == 0) return TRIOSEQ_OK;
+  if (!ws.have_props) {
+    trioseq_status st = device_props(&ws.dp);
+    if (st != TRIOSEQ_OK) return st;
+    ws.have_props = true;
+  }
+  const trioseq_plan_options o{-1, 4, 4, 0, 0, 2};  // the plane kernels' shape
+  Layout L;
+  trioseq_status st = build_layout(lens, offs, n, sc, o, ws.dp.cus * kWavesPerCuHint, &L, true);
+  if (st != TRIOSEQ_OK) return st;
+  int grid = 0, wpc = 0;
+  st = layout_grid(L, ws.dp, 0, &grid, &wpc);
+  if (st != TRIOSEQ_OK) return st;
+  hipError_t e;
+#define WS(call, what)                                  \
+  do {                                                  \
+    if ((e = (call)) != hipSuccess) return fail_hip(e, what); \
+  } while (0)
+  if (!ws.ctl.p) {
+    // [0] generation, [1] error flag, [64] queue head; the generation keeps
+    // growing across runs, so a zeroed pool's tags (0) are never current.
+    WS(ws_grow(ws.ctl, 512, true, s), "align: workspace");
+  }
+  WS(ws_grow(ws.desc, n * sizeof(TripletDesc), false, s), "align: workspace");
+  WS(ws_grow(ws.jobs, L.jobs.size() * sizeof(JobDesc), false, s), "align: workspace");
+  WS(ws_grow(ws.face, (uint64_t)grid * L.face_stride * 4, false, s), "align: workspace");
+  WS(ws_grow(ws.pool, L.pool_ints * 4, true, s), "align: workspace");
+  WS(ws_grow(ws.plane, plane_ints * 4, false, s), "align: workspace");
+  WS(ws_grow(ws.plane_off, n * 8, false, s), "align: workspace");
+  WS(ws_grow(ws.words, nwords * 4, false, s), "align: workspace");
+  WS(ws_grow(ws.scores, n * 4, false, s), "align: workspace");
+  if (!ws.bnd.p || L.lds_n0 > ws.bnd_n0) {
+    WS(hipStreamSynchronize(s), "align: workspace");
+    (void)hipFree(ws.bnd.p);
+    ws.bnd = PlaneWorkspace::Buf{};
+    WS(ws_grow(ws.bnd, boundary_ints(L.ks, L.lds_n0) * 4, false, s), "align: workspace");
+    ws.boundary = carve_boundary(L.ks, L.lds_n0, (int*)ws.bnd.p);
+    ws.bnd_n0 = L.lds_n0;
+    WS(launch_init_boundary(L.ks, ws.boundary, s), "align: boundary");
+  }
+  WS(hipStreamSynchronize(s), "align: workspace");  // the previous run's host copies
+  ws.h_desc.swap(L.desc);
+  ws.h_jobs.swap(L.jobs);
+  WS(hipMemcpyAsync(ws.desc.p, ws.h_desc.data(), n * sizeof(TripletDesc), hipMemcpyHostToDevice, s),
+     "align: upload");
+  WS(hipMemcpyAsync(ws.jobs.p, ws.h_jobs.data(), ws.h_jobs.size() * sizeof(JobDesc),
+                    hipMemcpyHostToDevice, s),
+     "align: upload");
+  WS(hipMemcpyAsync(ws.plane_off.p, plane_off, n * 8, hipMemcpyHostToDevice, s), "align: upload");
+  if (nwords) WS(hipMemcpyAsync(ws.words.p, words, nwords * 4, hipMemcpyHostToDevice, s), "align: upload");
+  int* ctl = (int*)ws.ctl.p;
+  WS(launch_prepare(ctl, ctl + 64, nullptr, 0, s), "align: prepare");
+  SweepArgs a = make_sweep_args((const uint32_t*)ws.words.p, (const TripletDesc*)ws.desc.p,
+                                (const JobDesc*)ws.jobs.p, (uint32_t)ws.h_jobs.size(), L.lds_n0,
+                                (int32_t*)ws.scores.p, ctl + 64, ctl, (int*)ws.face.p, L.face_stride,
+                                (int*)ws.pool.p, ws.boundary, nullptr, make_dev_scoring(sc));
+  a.plane = (int*)ws.plane.p;
+  a.plane_off = (const uint64_t*)ws.plane_off.p;
+  WS(launch_sweep(L.ks, L.modes, a, grid, s), "align: sweep");
+#undef WS
+  return TRIOSEQ_OK;
+}
 
 }  // namespace trioseq
 
@@ -638,7 +698,7 @@ extern "C" {
 static trioseq_status trioseq_plan_create_body(const uint32_t* lens, const uint64_t* word_off, size_t n,
                                    const trioseq_scoring* scp, const trioseq_plan_options* opts,
                                    trioseq_plan** out) {
-  return plan_create_impl(lens, word_off, n, scp, opts, false, nullptr, 0, out);
+  return plan_create_impl(lens, word_off, n, scp, opts, out);
 }
 
 static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t* d_scores,
@@ -650,8 +710,6 @@ static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t
   SweepArgs a = make_sweep_args(d_words, p->d_desc, p->d_jobs, p->njobs, p->lds_n0, d_scores,
                                 p->d_counter, p->d_ctl, p->d_face, p->face_stride, p->d_pface,
                                 p->bnd, p->d_red, p->sc);
-  a.plane = p->d_plane;
-  a.plane_off = p->d_plane_off;
   return launch_sweep(p->ks, p->modes, a, p->grid, s);
 }
 

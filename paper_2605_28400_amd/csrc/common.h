@@ -106,12 +106,32 @@ void apply_tuned(const uint32_t* lens, size_t n, int kind, trioseq_plan_options*
 trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested, int* grid,
                            int* waves_per_cu);
 
-// Traceback plane runs: a plan over triplets whose runs also write each
-// triplet's last slice (unshifted) to a device buffer of plane_ints ints,
-// triplet t at plane_off[t]; plan_planes gives that buffer.
-trioseq_status plan_create_planes(const uint32_t* lens, const uint64_t* off, size_t n,
-                                  const trioseq_scoring& sc, const uint64_t* plane_off,
-                                  uint64_t plane_ints, trioseq_plan** out);
-const int* plan_planes(const trioseq_plan* p);
+// Traceback plane runs: sweeps of triplets that also write each triplet's
+// last slice (unshifted), triplet t at plane + plane_off[t]. The device
+// buffers live in a PlaneWorkspace and are reused from run to run (grown when
+// a run needs more), so the levels of an alignment allocate almost nothing;
+// the generation word is shared by the runs, so face tags of an earlier run
+// never look current. Not thread-safe; runs are stream-ordered on `s`.
+struct PlaneWorkspace {
+  struct Buf {
+    void* p = nullptr;
+    uint64_t bytes = 0;
+  };
+  Buf ctl, desc, jobs, face, pool, bnd, red, plane, plane_off, words, scores;
+  Boundary boundary{};
+  uint32_t bnd_n0 = 0;
+  bool have_props = false;
+  DeviceProps dp{};
+  // Host copies of the last run's queue, alive until the next run (the
+  // uploads are asynchronous).
+  std::vector<TripletDesc> h_desc;
+  std::vector<JobDesc> h_jobs;
+  ~PlaneWorkspace();
+};
+// Lays out and sweeps n triplets (lens / word offsets on the host, words[0,
+// nwords) packed on the host), leaving the planes in ws.plane (device).
+trioseq_status run_planes(PlaneWorkspace& ws, const uint32_t* lens, const uint64_t* offs, size_t n,
+                          const uint32_t* words, size_t nwords, const trioseq_scoring& sc,
+                          const uint64_t* plane_off, uint64_t plane_ints, hipStream_t s);
 
 }  // namespace trioseq
