@@ -160,15 +160,15 @@ def per_triplet(ts, torch, trips, sample: int, stream, ref_scores=None, spread: 
         lens, off, words = ts.pack_batch([t])
         plan = ts.Plan(lens, off, sc=sc)
         w = torch.from_numpy(words.view(np.int32)).cuda()
-        sc = torch.zeros(1, dtype=torch.int32, device="cuda")
-        plan.run(w, sc, stream)
+        d_score = torch.zeros(1, dtype=torch.int32, device="cuda")
+        plan.run(w, d_score, stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plan.run(w, sc, stream)
+        plan.run(w, d_score, stream)
         torch.cuda.synchronize()
         busy += time.perf_counter() - t0
         cells += synth.cells(t)
-        alone.append(int(sc.cpu()[0]))
+        alone.append(int(d_score.cpu()[0]))
         plan.close()
     rec = {"value": round(cells / busy / 1e9, 3), "unit": "GCUPS", "ms": round(busy * 1e3, 3),
            "sample": f"{len(idx)} triplets ({'spread over' if spread else 'first of'} {len(trips)}), "
