@@ -349,7 +349,8 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: every workload here is measured on a single "
-              "MI355X (see DESIGN.md for how the path would shard).", file=sys.stderr)
+              "MI355X; independent triplets would shard across GPUs without collectives, "
+              "and no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2605_28400_amd as ts
