@@ -402,21 +402,27 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   L->face_stride = (stride + 63) / 64 * 64;
   L->pool_ints = pool;
 
-  // Job order: split triplets first (largest first, each panel after the
-  // panels it reads from: anti-diagonal order), then whole triplets longest
-  // first so the queue drains with short ones.
+  // Job order: split triplets' panels first, by anti-diagonal d = pj + pk
+  // across all split triplets (largest first within a diagonal), so every
+  // panel comes after the panels it reads from and several split triplets
+  // fill their pipelines together; then whole triplets longest first so the
+  // queue drains with short ones.
   std::vector<size_t> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
   std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
   L->jobs.clear();
   L->jobs.reserve(n + panels);
-  for (size_t t : idx) {
-    if (!split[t]) continue;
-    const uint32_t PJ = L->desc[t].len[1] / H + 1, PK = L->desc[t].len[2] / W + 1;
-    for (uint32_t d = 0; d + 1 < PJ + PK; ++d)
+  uint32_t diagonals = 0;
+  for (size_t t : idx)
+    if (split[t]) diagonals = std::max(diagonals, L->desc[t].len[1] / H + L->desc[t].len[2] / W + 1);
+  for (uint32_t d = 0; d < diagonals; ++d)
+    for (size_t t : idx) {
+      if (!split[t]) continue;
+      const uint32_t PJ = L->desc[t].len[1] / H + 1, PK = L->desc[t].len[2] / W + 1;
+      if (d + 1 >= PJ + PK) continue;
       for (uint32_t pj = (d >= PK ? d - PK + 1 : 0); pj <= std::min(d, PJ - 1); ++pj)
         L->jobs.push_back(JobDesc{(uint32_t)t, pj * PK + (d - pj)});
-  }
+    }
   for (size_t t : idx)
     if (!split[t]) L->jobs.push_back(JobDesc{(uint32_t)t, kWholeTriplet});
   return TRIOSEQ_OK;
