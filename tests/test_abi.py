@@ -172,3 +172,22 @@ def test_score_batch_packed_rejects_bad_input():
     assert L.trioseq_score_batch_packed(None, None, None, 3, ctypes.byref(ts.scoring()), None, None) == -1
     assert L.trioseq_score_batch_packed(None, None, None, 3, None, None, None) == -1
     assert L.trioseq_score_batch_packed(None, None, None, 0, ctypes.byref(ts.scoring()), None, None) == 0
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # No CPU fallback: without the built library every scoring call raises.
+    import subprocess
+    import sys as _sys
+    code = (
+        "import paper_2605_28400_amd as ts\n"
+        f"ts.LIB_PATH = {str(tmp_path / 'absent.so')!r}\n"
+        "ts._lib = None\n"
+        "try:\n"
+        "    ts.score(('ACGT', 'ACG', 'AC'))\n"
+        "except ImportError as e:\n"
+        "    print('raised', e)\n"
+        "else:\n"
+        "    print('no error')\n")
+    out = subprocess.run([_sys.executable, "-c", code], capture_output=True, text=True,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert "raised" in out.stdout and "absent.so" in out.stdout, out.stdout + out.stderr

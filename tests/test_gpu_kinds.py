@@ -189,3 +189,22 @@ def test_batch_8192_sampled(torch_cuda, name, kind, okind):
     got, _ = run_plan(torch_cuda, wl.triplets, ts.scoring(kind=kind))
     assert (got[idx] == want).all(), [(int(q), int(got[q]), int(w)) for q, w in zip(idx, want)
                                       if got[q] != w][:5]
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_autotune_is_parity_gated_for_kinds(torch_cuda, name, kind, okind):
+    # The autotuner tries every shape compiled for the kind (4x4 and 8x4 here),
+    # keeps only candidates whose scores equal the reference configuration's,
+    # and a plan created afterwards with default options takes its choice.
+    torch = torch_cuda
+    rng = np.random.default_rng(48)
+    trips = related(rng, 80, 20, 160)
+    lens, off, words = ts.pack_batch(trips)
+    d_words = torch.from_numpy(words.view(np.int32)).cuda()
+    sc = ts.scoring(kind=kind)
+    say(f"{name} autotune")
+    res = ts.autotune(lens, off, d_words, sc=sc, reps=1)
+    assert res["tried"] >= 2 and res["rejected"] == 0
+    got, info = run_plan(torch, trips, sc)
+    assert (info["tile_rows"], info["tile_cols"]) == (res["best"]["tile_rows"], res["best"]["tile_cols"])
+    assert (got == want_of(trips, okind)).all()
