@@ -236,6 +236,17 @@ struct trioseq_plan {
   Boundary bnd{};
   int* d_red = nullptr;      // per-triplet reduction pairs (semi-global, local)
   uint32_t red_pairs = 0;
+  // Half-split scoring of a lone triplet (see half_split_layout).
+  bool half = false;
+  uint32_t h_words_n = 0, h_nchunk = 0;
+  uint32_t* d_hwords = nullptr;     // the two halves' sequences, gathered every run
+  GatherDesc* d_gather = nullptr;   // 6 gather descriptors
+  int* d_plane = nullptr;           // the two last-slice planes
+  uint64_t* d_plane_off = nullptr;  // {0, plane ints}
+  SplitDesc* d_sdesc = nullptr;     // the meeting box
+  uint32_t* d_chunk_box = nullptr;  // all 0 (one box)
+  int* d_partial = nullptr;         // per chunk: best, index
+  int32_t* d_hscores = nullptr;     // the halves' own scores (unused)
   // graph replay
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
@@ -258,6 +269,9 @@ static void plan_free(trioseq_plan* p) {
   (void)hipFree(p->d_pface);
   (void)hipFree(p->d_bnd);
   (void)hipFree(p->d_red);
+  for (void* q : {(void*)p->d_hwords, (void*)p->d_gather, (void*)p->d_plane, (void*)p->d_plane_off,
+                  (void*)p->d_sdesc, (void*)p->d_chunk_box, (void*)p->d_partial, (void*)p->d_hscores})
+    (void)hipFree(q);
   delete p;
 }
 
@@ -513,6 +527,57 @@ trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested
 
 }  // namespace trioseq
 
+// Half-split scoring of a lone global triplet. Its longest sequence S_a is
+// cut at mid; the first half (S_a[0, mid), S_r, S_c) is swept forward and the
+// second half reversed (rev S_a[mid, n_a), rev S_r, rev S_c), concurrently,
+// both writing their last slice, a plane over (S_r, S_c). Every alignment
+// crosses the slice a = mid, so the score is the best F[p][q] + R[P-p][Q-q]
+// over that plane (the crossing identity Hirschberg's method rests on). Each
+// half's pipeline of panels is as long as the whole triplet's but sweeps half
+// the slices, and the two fill together: the lone triplet finishes sooner.
+constexpr uint32_t kHalfSplitMin = 256;  // shortest longest-sequence for it
+struct HalfSplit {
+  uint32_t lens[6];
+  uint64_t offs[6];      // word offsets in the gathered buffer
+  GatherDesc gather[6];
+  uint32_t words = 0;    // gathered words
+  uint32_t rows = 0, cols = 0;
+};
+
+static bool half_split_layout(const uint32_t* lens, const uint64_t* word_off, HalfSplit* h) {
+  int ax = 0;
+  for (int q = 1; q < 3; ++q)
+    if (lens[q] > lens[ax]) ax = q;
+  const uint32_t na = lens[ax];
+  if (na < kHalfSplitMin || (na + 1) / 2 > (uint32_t)kMaxSweepLen) return false;
+  const int r = ax == 0 ? 1 : 0, c = ax == 2 ? 1 : 2;
+  const uint32_t mid = na / 2;
+  uint64_t src[3];
+  if (word_off) {
+    for (int q = 0; q < 3; ++q) src[q] = word_off[q];
+  } else {
+    uint64_t tw = 0;
+    trioseq_packed_layout(lens, 1, src, &tw);
+  }
+  const int order[3] = {ax, r, c};
+  uint64_t w = 0;
+  for (int half = 0; half < 2; ++half)
+    for (int k = 0; k < 3; ++k) {
+      const int q = order[k];
+      const uint32_t start = (k == 0 && half == 1) ? mid : 0;
+      const uint32_t len = k == 0 ? (half == 0 ? mid : na - mid) : lens[q];
+      const int i = 3 * half + k;
+      h->lens[i] = len;
+      h->offs[i] = w;
+      h->gather[i] = GatherDesc{src[q], w, start, len, (uint32_t)half};
+      w += (len + 15) / 16;
+    }
+  h->words = (uint32_t)w;
+  h->rows = lens[r] + 1;
+  h->cols = lens[c] + 1;
+  return true;
+}
+
 static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* word_off, size_t n,
                                        const trioseq_scoring* scp, const trioseq_plan_options* opts,
                                        trioseq_plan** out) {
@@ -520,6 +585,7 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
   if (!scp) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: scoring is NULL");
   trioseq_plan_options o{-1, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
+  const bool defaults = o.engine == -1 && !o.tile_rows && !o.tile_cols && !o.waves_per_simd && !o.grid;
   if (!o.tile_rows && !o.tile_cols && !o.waves_per_simd && lens) apply_tuned(lens, n, scp->kind, &o);
   // Inputs are validated (by the layout) before the device is touched; the
   // layout is redone if the device's size changes the split rule's hint.
@@ -527,14 +593,20 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
   int hint = 256 * kWavesPerCuHint;
   trioseq_status st = build_layout(lens, word_off, n, *scp, o, hint, &L);
   if (st != TRIOSEQ_OK) return st;
+  // A lone global triplet under the automatic options is scored by halves.
+  HalfSplit hs;
+  const bool half = n == 1 && defaults && scp->kind == kGlobal && half_split_layout(lens, word_off, &hs);
+  const trioseq_plan_options ho{-1, 4, 4, 0, 0, 2};  // the plane kernels' shape
   DeviceProps dp;
   st = device_props(&dp);
   if (st != TRIOSEQ_OK) return st;
-  if (dp.cus * kWavesPerCuHint != hint) {
+  if (half || dp.cus * kWavesPerCuHint != hint) {
     hint = dp.cus * kWavesPerCuHint;
-    st = build_layout(lens, word_off, n, *scp, o, hint, &L);
+    st = half ? build_layout(hs.lens, hs.offs, 2, *scp, ho, hint, &L, true)
+              : build_layout(lens, word_off, n, *scp, o, hint, &L);
     if (st != TRIOSEQ_OK) return st;
   }
+  const size_t nd = L.desc.size();  // triplets the kernels see
 
   trioseq_plan* p = new (std::nothrow) trioseq_plan;
   if (!p) return fail(TRIOSEQ_ERR_NOMEM, "plan: host allocation");
@@ -567,10 +639,10 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
   if ((e = hipMalloc((void**)&p->d_counter, 256)) != hipSuccess) return hip_bail(e, "hipMalloc");
   if ((e = hipMalloc((void**)&p->d_ctl, 256)) != hipSuccess) return hip_bail(e, "hipMalloc");
   if ((e = hipMemset(p->d_ctl, 0, 256)) != hipSuccess) return hip_bail(e, "hipMemset");
-  if (n) {
-    if ((e = hipMalloc((void**)&p->d_desc, n * sizeof(TripletDesc))) != hipSuccess)
+  if (nd) {
+    if ((e = hipMalloc((void**)&p->d_desc, nd * sizeof(TripletDesc))) != hipSuccess)
       return hip_bail(e, "hipMalloc desc");
-    if ((e = hipMemcpy(p->d_desc, L.desc.data(), n * sizeof(TripletDesc), hipMemcpyHostToDevice)) !=
+    if ((e = hipMemcpy(p->d_desc, L.desc.data(), nd * sizeof(TripletDesc), hipMemcpyHostToDevice)) !=
         hipSuccess)
       return hip_bail(e, "hipMemcpy desc");
     if ((e = hipMalloc((void**)&p->d_jobs, L.jobs.size() * sizeof(JobDesc))) != hipSuccess)
@@ -599,7 +671,29 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_bail(e, "boundary init");
   p->workspace_bytes = face_bytes + pool_bytes + bnd_ints * sizeof(int) +
                        (uint64_t)p->red_pairs * 2 * sizeof(int) +
-                       n * sizeof(TripletDesc) + L.jobs.size() * sizeof(JobDesc) + 512;
+                       nd * sizeof(TripletDesc) + L.jobs.size() * sizeof(JobDesc) + 512;
+  if (half) {
+    p->half = true;
+    p->h_words_n = hs.words;
+    const uint64_t pints = (uint64_t)hs.rows * hs.cols;
+    p->h_nchunk = (uint32_t)((pints + kSplitChunk - 1) / kSplitChunk);
+    const uint64_t plane_off[2] = {0, pints};
+    const SplitDesc box{0, pints, hs.rows, hs.cols, 0, p->h_nchunk};
+    if ((e = hipMalloc((void**)&p->d_hwords, std::max<uint64_t>(hs.words, 1) * 4)) != hipSuccess ||
+        (e = hipMalloc((void**)&p->d_gather, sizeof hs.gather)) != hipSuccess ||
+        (e = hipMalloc((void**)&p->d_plane, 2 * pints * 4)) != hipSuccess ||
+        (e = hipMalloc((void**)&p->d_plane_off, sizeof plane_off)) != hipSuccess ||
+        (e = hipMalloc((void**)&p->d_sdesc, sizeof box)) != hipSuccess ||
+        (e = hipMalloc((void**)&p->d_chunk_box, p->h_nchunk * 4)) != hipSuccess ||
+        (e = hipMalloc((void**)&p->d_partial, p->h_nchunk * 8)) != hipSuccess ||
+        (e = hipMalloc((void**)&p->d_hscores, 8)) != hipSuccess ||
+        (e = hipMemcpy(p->d_gather, hs.gather, sizeof hs.gather, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->d_plane_off, plane_off, sizeof plane_off, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->d_sdesc, &box, sizeof box, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(p->d_chunk_box, 0, p->h_nchunk * 4)) != hipSuccess)
+      return hip_bail(e, "half-split buffers");
+    p->workspace_bytes += 2 * pints * 4 + (uint64_t)hs.words * 4 + p->h_nchunk * 12 + 256;
+  }
   if (p->use_graph) {
     if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
       return hip_bail(e, "hipStreamCreate");
@@ -711,6 +805,19 @@ static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t
                                hipStream_t s) {
   if (p->n == 0) return hipSuccess;
   hipError_t e;
+  if (p->half) {
+    // Gather the halves, sweep both (writing their last slices), meet.
+    if ((e = launch_gather(d_words, p->d_gather, 6, p->h_words_n, p->d_hwords, s)) != hipSuccess) return e;
+    if ((e = launch_prepare(p->d_ctl, p->d_counter, nullptr, 0, s)) != hipSuccess) return e;
+    SweepArgs a = make_sweep_args(p->d_hwords, p->d_desc, p->d_jobs, p->njobs, p->lds_n0, p->d_hscores,
+                                  p->d_counter, p->d_ctl, p->d_face, p->face_stride, p->d_pface, p->bnd,
+                                  nullptr, p->sc);
+    a.plane = p->d_plane;
+    a.plane_off = p->d_plane_off;
+    if ((e = launch_sweep(p->ks, p->modes, a, p->grid, s)) != hipSuccess) return e;
+    return launch_meet(p->d_sdesc, p->d_chunk_box, p->h_nchunk, p->d_plane, p->d_partial, p->d_ctl + 1,
+                       d_scores, s);
+  }
   if ((e = launch_prepare(p->d_ctl, p->d_counter, p->d_red, p->red_pairs, s)) != hipSuccess)
     return e;
   SweepArgs a = make_sweep_args(d_words, p->d_desc, p->d_jobs, p->njobs, p->lds_n0, d_scores,

@@ -180,7 +180,58 @@ __global__ void __launch_bounds__(64) k_leaf(LeafArgs a) {
   a.ncols[leaf] = (uint32_t)n;
 }
 
+// Gather: one thread per output word packs 16 residues of one output
+// sequence (forward or reversed) from the caller's packed sequences.
+__global__ void __launch_bounds__(256) k_gather(const uint32_t* __restrict__ in,
+                                                const GatherDesc* __restrict__ d, uint32_t n,
+                                                uint32_t words_out, uint32_t* __restrict__ out) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= words_out) return;
+  // The output sequence holding word w (sequences start on fresh words).
+  uint32_t q = 0;
+  while (q + 1 < n && d[q + 1].dst_off <= w) ++q;
+  const GatherDesc g = d[q];
+  const uint32_t first = (uint32_t)(w - g.dst_off) * 16;
+  uint32_t v = 0;
+  for (uint32_t b = 0; b < 16; ++b) {
+    const uint32_t p = first + b;
+    if (p >= g.len) break;
+    const uint32_t src = g.reverse ? g.start + g.len - 1 - p : g.start + p;
+    v |= leaf_residue(in, g.src_off, src) << (2 * b);
+  }
+  out[w] = v;
+}
+
+// Meet: one wave folds the chunks' best values of box 0 into the score.
+__global__ void __launch_bounds__(64) k_meet_final(const SplitDesc* __restrict__ box,
+                                                   const int* __restrict__ partial,
+                                                   const int* __restrict__ err, int32_t* out) {
+  const SplitDesc d = box[0];
+  int best = INT32_MIN;
+  for (uint32_t c = threadIdx.x; c < d.nchunk; c += 64) best = max(best, partial[2 * (d.chunk0 + c)]);
+  for (int m = 32; m >= 1; m >>= 1) best = max(best, __shfl_xor(best, m, 64));
+  if (threadIdx.x == 0) {
+    const bool bad = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    __hip_atomic_store(out, bad ? INT32_MIN : best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_gather(const uint32_t* in, const GatherDesc* d, uint32_t n, uint32_t words_out,
+                         uint32_t* out, hipStream_t s) {
+  if (words_out == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3((words_out + 255) / 256), dim3(256), 0, s, in, d, n, words_out, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_meet(const SplitDesc* box, const uint32_t* chunk_box, uint32_t nchunks,
+                       const int* planes, int* partial, const int* err, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_split_part, dim3(nchunks), dim3(256), 0, s, planes, box, chunk_box, nchunks,
+                     partial);
+  hipLaunchKernelGGL(k_meet_final, dim3(1), dim3(64), 0, s, box, partial, err, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_split(const int* planes, const SplitDesc* boxes, uint32_t n, const uint32_t* chunk_box,
                         uint32_t nchunks, int* partial, int* out, hipStream_t s) {

@@ -257,3 +257,28 @@ def test_score_batch_packed_device_buffers(torch_cuda):
         ts.score_batch_packed(d_words, d_off, d_len, d_scores, len(trips), stream=s2)
     torch.cuda.synchronize()
     assert (d_scores.cpu().numpy() == oracle_scores(trips)).all()
+
+
+def test_lone_triplet_half_split(torch_cuda):
+    # A lone global triplet under automatic options is scored by halves (its
+    # longest sequence cut in two, the second half swept reversed, the two
+    # last-slice planes met). Compared with the classic split engine and the
+    # oracle on odd lengths, ties for the longest, empty and length-1
+    # sequences, and graph replays.
+    rng = np.random.default_rng(30)
+    shapes = [(256, 40, 33), (257, 257, 100), (300, 0, 0), (0, 311, 7), (1, 1, 400), (290, 290, 290),
+              (64, 333, 1), (513, 200, 150)]
+    for q, n in enumerate(shapes):
+        if q % 2:
+            t = synth.mutated_triplet(rng, max(n), 0.1, lens=n)
+        else:
+            t = tuple(synth.uniform_seq(rng, m) for m in n)
+        want = oracle.score(t)
+        say(f"half split lens={n}")
+        got_half, info = run_plan(torch_cuda, [t], engine=-1)
+        got_classic, _ = run_plan(torch_cuda, [t], engine=1)
+        assert int(got_half[0]) == int(got_classic[0]) == want, (n, int(got_half[0]), int(got_classic[0]), want)
+        assert ts.score(t) == want
+    t = synth.mutated_triplet(rng, 400, 0.05, lens=(400, 380, 390))
+    outs, _ = run_plan(torch_cuda, [t], engine=-1, use_graph=True, reps=4)
+    assert all(int(o[0]) == oracle.score(t) for o in outs)
