@@ -38,21 +38,36 @@ WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served", "tr
 # WRITE_SIZE runs scaled by the same counters on a plain 1 GiB copy (summaries
 # with the commands are under profiles/). Each figure holds only for the kernel
 # source it was measured on; for any other source the field is null.
-# Keyed by (workload, kind, lane tile): the autotuner may pick another tile.
+# Keyed by (workload, kind, lane tile, path): the autotuner may pick another
+# tile, and a lone global triplet under automatic options is scored by halves.
 TRAFFIC = {
-    ("single_1024x1000x1048", "global", "4x4"): (1.5689e9, "5b986628d09c52c4"),
-    ("batch_8192_len100-400", "global", "8x4"): (7.2410e10, "5b986628d09c52c4"),
-    ("single_4096x4000x4150", "global", "4x4"): (7.9174e10, "5b986628d09c52c4"),
-    ("single_1024x1000x1048", "local", "4x4"): (1.6522e9, "5b986628d09c52c4"),
-    ("batch_8192_len100-400", "local", "4x4"): (9.7230e10, "5b986628d09c52c4"),
-    ("single_1024x1000x1048", "semi-global", "4x4"): (1.6210e9, "5b986628d09c52c4"),
-    ("batch_8192_len100-400", "semi-global", "8x4"): (7.3193e10, "5b986628d09c52c4"),
+    ("batch_8192_len100-400", "global", "8x4", "batch"): (7.2410e10, "5b986628d09c52c4"),
+    ("single_1024x1000x1048", "global", "4x4", "halves"): (1.5177e9, "5b986628d09c52c4"),
+    ("single_4096x4000x4150", "global", "4x4", "halves"): (7.7511e10, "5b986628d09c52c4"),
+    ("single_1024x1000x1048", "global", "4x4", "split"): (1.5689e9, "5b986628d09c52c4"),
+    ("single_4096x4000x4150", "global", "4x4", "split"): (7.9174e10, "5b986628d09c52c4"),
+    ("single_1024x1000x1048", "local", "4x4", "split"): (1.6522e9, "5b986628d09c52c4"),
+    ("batch_8192_len100-400", "local", "4x4", "batch"): (9.7230e10, "5b986628d09c52c4"),
+    ("single_1024x1000x1048", "semi-global", "4x4", "split"): (1.6210e9, "5b986628d09c52c4"),
+    ("batch_8192_len100-400", "semi-global", "8x4", "batch"): (7.3193e10, "5b986628d09c52c4"),
 }
 
 
-def measured_traffic(workload_name: str, kind: str, tile: str):
+def scoring_path(trips, kind: str, engine: int, tile: str) -> str:
+    """Which kernels a plan runs: "halves" (a lone global triplet whose longest
+    sequence has at least 256 residues, automatic options: its two halves swept
+    concurrently with the last-slice plane variant, then met), "split" (panel
+    jobs), or "batch" (several triplets)."""
+    if len(trips) != 1:
+        return "batch"
+    if kind == "global" and engine == -1 and tile == "0x0" and max(s.size for s in trips[0]) >= 256:
+        return "halves"
+    return "split"
+
+
+def measured_traffic(workload_name: str, kind: str, tile: str, path: str):
     import hashlib
-    entry = TRAFFIC.get((workload_name, kind, tile))
+    entry = TRAFFIC.get((workload_name, kind, tile, path))
     if entry is None:
         return None
     src = os.path.join(ROOT, "paper_2605_28400_amd", "csrc", "sweep.hip")
@@ -374,6 +389,7 @@ def main():
         tuned = ts.autotune(lens, off, d_words, sc=sc, reps=2)
     plan = ts.Plan(lens, off, sc=sc, engine=args.engine, tile=(rj, rk), use_graph=bool(args.graph))
     info = plan.info()
+    path = scoring_path(trips, args.kind, args.engine, args.tile)
     d_scores = torch.zeros(len(trips), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 
@@ -407,21 +423,24 @@ def main():
         "config": {"workload": workload.name, "triplets": len(trips), "cells": int(cells),
                    "seed": workload.seed, "scoring": "match +1, mismatch -1, gap -2",
                    "kind": args.kind,
-                   "engine": ["whole-triplet", "split", "mixed"][info["engine"]],
+                   "engine": ["whole-triplet", "split", "mixed"][info["engine"]], "path": path,
                    "tile": f"{info['tile_rows']}x{info['tile_cols']}", "grid": info["grid"],
                    "hip_graph": bool(args.graph), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOP/s",
                      "frac": round(achieved / PEAK_INT32_TOPS, 4),
                      "traffic": measured_traffic(workload.name, args.kind,
-                                                 f"{info['tile_rows']}x{info['tile_cols']}"),
+                                                 f"{info['tile_rows']}x{info['tile_cols']}", path),
                      "kernel_ms": round(ms_events, 4), "ops_per_cell": ops,
                      # Eq. 1 counted as 7 sums and a 7-way maximum (13 two-input operations).
                      "frac_13_ops_per_cell": round(cells * (ops + 6) / (ms_events * 1e-3) / 1e12
                                                    / PEAK_INT32_TOPS, 4),
-                     "kernel": ["k_sweep (persistent job queue, whole-triplet jobs)",
-                                "k_panel (persistent job queue, two-wave panel workgroups)",
-                                "k_sweep (persistent job queue, whole-triplet and panel jobs)"][info["engine"]]},
+                     "kernel": ("k_panel plane variant (two halves swept concurrently, two-wave "
+                                "panel workgroups) + gather + meet; time of the whole plan run"
+                                if path == "halves" else
+                                ["k_sweep (persistent job queue, whole-triplet jobs)",
+                                 "k_panel (persistent job queue, two-wave panel workgroups)",
+                                 "k_sweep (persistent job queue, whole-triplet and panel jobs)"][info["engine"]])},
     }
     # End to end through the host API: pack, upload, lay out, sweep, download.
     ts.score_batch(trips[:1], sc)
