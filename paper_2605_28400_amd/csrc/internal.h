@@ -126,7 +126,7 @@ bool shape_supported(const KernelShape& ks, int kind);
 // Traceback (traceback.hip). A split box: the forward and reversed planes
 // (ints from the plane buffer base), rows x cols entries each, reduced in
 // nchunk chunks of kSplitChunk cells numbered from chunk0.
-constexpr uint32_t kSplitChunk = 4096;
+constexpr uint32_t kSplitChunk = 16384;
 struct SplitDesc {
   uint64_t fwd, bwd;
   uint32_t rows, cols;
