@@ -20,6 +20,8 @@ __device__ __forceinline__ uint32_t leaf_residue(const uint32_t* __restrict__ wo
   return (words[off + (p >> 4)] >> ((p & 15u) << 1)) & 3u;
 }
 
+constexpr int kSplitBatch = 8;
+
 // Split, stage 1: one workgroup per chunk of kSplitChunk cells of one box's
 // plane; its best F[p][q] + R[P-p][Q-q] and the smallest linear index
 // p * cols + q reaching it.
@@ -39,12 +41,26 @@ __global__ void __launch_bounds__(256) k_split_part(const int* __restrict__ plan
   const uint32_t hi = min(cells, lo + kSplitChunk);
   int best = INT32_MIN;
   uint32_t bidx = 0xFFFFFFFFu;
-  for (uint32_t q = lo + threadIdx.x; q < hi; q += blockDim.x) {
-    const uint32_t p = q / d.cols, c = q - p * d.cols;
-    const int v = F[q] + R[(d.rows - 1 - p) * d.cols + (d.cols - 1 - c)];
-    if (v > best) {  // q grows, so the first maximum of this thread is kept
-      best = v;
-      bidx = q;
+  // kSplitBatch cells per thread per pass, their loads issued together: one
+  // workgroup covers a whole chunk, so a pass at a time would wait out a full
+  // memory latency per cell.
+  for (uint32_t q0 = lo + threadIdx.x; q0 < hi; q0 += kSplitBatch * blockDim.x) {
+    int v[kSplitBatch];
+#pragma unroll
+    for (int u = 0; u < kSplitBatch; ++u) {
+      // Cells past the chunk load its last cell (no branch between the
+      // loads) and are then discarded.
+      const uint32_t q = q0 + u * blockDim.x, qc = min(q, hi - 1);
+      const uint32_t p = qc / d.cols, c = qc - p * d.cols;
+      const int s = F[qc] + R[(d.rows - 1 - p) * d.cols + (d.cols - 1 - c)];
+      v[u] = q < hi ? s : INT32_MIN;
+    }
+#pragma unroll
+    for (int u = 0; u < kSplitBatch; ++u) {
+      if (v[u] > best) {  // q grows with u, so the first maximum of this thread is kept
+        best = v[u];
+        bidx = q0 + u * blockDim.x;
+      }
     }
   }
   s_val[threadIdx.x] = best;
