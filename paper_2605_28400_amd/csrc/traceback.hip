@@ -20,7 +20,7 @@ __device__ __forceinline__ uint32_t leaf_residue(const uint32_t* __restrict__ wo
   return (words[off + (p >> 4)] >> ((p & 15u) << 1)) & 3u;
 }
 
-constexpr int kSplitBatch = 8;
+constexpr int kSplitBatch = 32;
 
 // Split, stage 1: one workgroup per chunk of kSplitChunk cells of one box's
 // plane; its best F[p][q] + R[P-p][Q-q] and the smallest linear index
