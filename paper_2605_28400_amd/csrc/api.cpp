@@ -806,9 +806,11 @@ static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t
   if (p->n == 0) return hipSuccess;
   hipError_t e;
   if (p->half) {
-    // Gather the halves, sweep both (writing their last slices), meet.
-    if ((e = launch_gather(d_words, p->d_gather, 6, p->h_words_n, p->d_hwords, s)) != hipSuccess) return e;
-    if ((e = launch_prepare(p->d_ctl, p->d_counter, nullptr, 0, s)) != hipSuccess) return e;
+    // Gather the halves (and prepare the run), sweep both (writing their
+    // last slices), meet.
+    if ((e = launch_gather(d_words, p->d_gather, 6, p->h_words_n, p->d_hwords, p->d_ctl, p->d_counter, s)) !=
+        hipSuccess)
+      return e;
     SweepArgs a = make_sweep_args(p->d_hwords, p->d_desc, p->d_jobs, p->njobs, p->lds_n0, p->d_hscores,
                                   p->d_counter, p->d_ctl, p->d_face, p->face_stride, p->d_pface, p->bnd,
                                   nullptr, p->sc);

@@ -158,13 +158,14 @@ constexpr uint64_t kLeafCells = 4096;
 // Half-split scoring of a lone triplet. One output sequence of the gather:
 // len residues, residue p taken from the packed sequence at word src_off,
 // residue start + p (or start + len - 1 - p if reverse), written packed from
-// word dst_off.
+// word dst_off. With ctl non-null the same launch also does launch_prepare's
+// work for a run without reduction pairs (ctl, counter as there).
 struct GatherDesc {
   uint64_t src_off, dst_off;
   uint32_t start, len, reverse;
 };
 hipError_t launch_gather(const uint32_t* in, const GatherDesc* d, uint32_t n, uint32_t words_out,
-                         uint32_t* out, hipStream_t s);
+                         uint32_t* out, int* ctl, int* counter, hipStream_t s);
 // After launch_split's first stage over one box: out[0] = the best F + R of
 // box 0, or INT32_MIN if err[0] is set (a wait of the run gave up).
 hipError_t launch_meet(const SplitDesc* box, const uint32_t* chunk_box, uint32_t nchunks,

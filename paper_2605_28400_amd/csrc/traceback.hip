@@ -200,8 +200,17 @@ __global__ void __launch_bounds__(64) k_leaf(LeafArgs a) {
 // sequence (forward or reversed) from the caller's packed sequences.
 __global__ void __launch_bounds__(256) k_gather(const uint32_t* __restrict__ in,
                                                 const GatherDesc* __restrict__ d, uint32_t n,
-                                                uint32_t words_out, uint32_t* __restrict__ out) {
+                                                uint32_t words_out, uint32_t* __restrict__ out,
+                                                int* __restrict__ ctl, int* __restrict__ counter) {
   const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  // With ctl given, also the per-run preparation of the sweep that follows
+  // (next generation, error flag cleared, queue head zeroed), saving its
+  // launch: nothing here reads these words.
+  if (ctl && w == 0) {
+    ctl[0] = ctl[0] + 1;
+    ctl[1] = 0;
+    counter[0] = 0;
+  }
   if (w >= words_out) return;
   // The output sequence holding word w (sequences start on fresh words).
   uint32_t q = 0;
@@ -235,9 +244,10 @@ __global__ void __launch_bounds__(64) k_meet_final(const SplitDesc* __restrict__
 }  // namespace
 
 hipError_t launch_gather(const uint32_t* in, const GatherDesc* d, uint32_t n, uint32_t words_out,
-                         uint32_t* out, hipStream_t s) {
-  if (words_out == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather, dim3((words_out + 255) / 256), dim3(256), 0, s, in, d, n, words_out, out);
+                         uint32_t* out, int* ctl, int* counter, hipStream_t s) {
+  if (words_out == 0 && !ctl) return hipSuccess;
+  const uint32_t blocks = words_out == 0 ? 1 : (words_out + 255) / 256;
+  hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(256), 0, s, in, d, n, words_out, out, ctl, counter);
   return hipGetLastError();
 }
 
