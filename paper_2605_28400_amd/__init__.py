@@ -207,7 +207,8 @@ def _triplet(t, keep: list) -> Triplet:
 
 
 def score(triplet, sc: Scoring | None = None) -> int:
-    """Exact global SOP score of one triplet (ASCII strings/bytes or code arrays)."""
+    """Exact SOP score of one triplet (ASCII strings/bytes or code arrays):
+    global, semi-global or local as ``sc.kind`` says (global by default)."""
     keep: list = []
     tr = _triplet(triplet, keep)
     out = ctypes.c_int32()
