@@ -99,13 +99,20 @@ trioseq_status trioseq_score(const trioseq_triplet* t, const trioseq_scoring* sc
 
 /* Scores of n triplets, computed together (one persistent launch for the
  * batch; triplets that would hold the launch up are split over many
- * wavefronts). Synchronous: returns when scores[0..n) (host memory) are
- * written. Work is issued on hip_stream. */
+ * wavefronts). This is the paper's host pipeline (Section IV, Approach
+ * Overview: triplets read on the host are sent to the GPU, the optimal
+ * scores come back to the host), for a whole batch at once. t[0..n) are host
+ * ASCII triplets; scores[0..n) is host memory owned by the caller. The call
+ * keeps no pointer after it returns. Synchronous: returns when scores[0..n)
+ * are written. Work is issued on hip_stream. The device workspace of the
+ * last few batch shapes is cached per thread and reused when the same
+ * lengths come again (no allocation on such calls). */
 trioseq_status trioseq_score_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
                                    int32_t* scores, void* hip_stream);
 
 /* Scores of n triplets whose packed residues are already in device memory
- * (e.g. torch-owned buffers). d_words: packed residues (trioseq_pack layout);
+ * (e.g. torch-owned buffers): the host pipeline of Section IV (Approach
+ * Overview) with the sequences already uploaded. d_words: packed residues (trioseq_pack layout);
  * d_word_off / d_len: 3n entries each in device memory, sequence s of triplet
  * t starting at word d_word_off[3t+s] with d_len[3t+s] residues; d_scores: n
  * int32 in device memory. The offsets and lengths are read back first (the
@@ -142,7 +149,10 @@ trioseq_status trioseq_align(const trioseq_triplet* t, const trioseq_scoring* sc
 trioseq_status trioseq_align_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
                                    char* rows, uint32_t* ncols, int32_t* scores, void* hip_stream);
 
-/* ---- Plans: device-resident batches (inputs already in HBM). ---------- */
+/* ---- Plans: device-resident batches (inputs already in HBM). ----------
+ * The host side of Section IV's pipeline split in two: the layout of a batch
+ * (which sequence is swept, which triplets are split into panel jobs, the
+ * job order) is made once, and each run only launches the kernels. */
 
 typedef struct trioseq_plan trioseq_plan;
 
@@ -205,7 +215,11 @@ trioseq_status trioseq_autotune(const uint32_t* lens, const uint64_t* word_off, 
                                 const trioseq_scoring* sc, const uint32_t* d_words, int32_t reps,
                                 void* hip_stream, trioseq_tune_result* out);
 
-/* ---- Serving: continuous batching of a request stream. ---------------- */
+/* ---- Serving: continuous batching of a request stream. ----------------
+ * Section IV's host pipeline (triplets in, optimal scores back to the host)
+ * run as a service: requests are admitted by device footprint into rounds
+ * while earlier rounds still run, and each score reaches the host as soon as
+ * its own triplet is done. */
 
 typedef struct trioseq_server trioseq_server;
 
@@ -215,6 +229,9 @@ typedef struct trioseq_serve_config {
   uint32_t max_len;          /* longest accepted sequence */
   uint32_t max_queue;        /* pending requests before submit returns BUSY */
   uint32_t max_batch;        /* triplets per device round (0 = automatic) */
+  uint32_t max_inflight;     /* rounds in flight at once, each with its own
+                                device arena and stream (0 = 4; at most 16);
+                                max_device_bytes is shared among them */
 } trioseq_serve_config;
 
 typedef struct trioseq_result {
@@ -230,6 +247,7 @@ typedef struct trioseq_serve_stats {
   double cells;           /* sum of a*b*c over completed requests */
   double busy_s;          /* wall time with at least one round in flight */
   double p50_ns, p99_ns;  /* submit-to-result latency over completed requests */
+  double gcups;           /* cells / busy_s / 1e9: throughput while work was in flight */
 } trioseq_serve_stats;
 
 trioseq_status trioseq_serve_create(const trioseq_serve_config* cfg, const trioseq_scoring* sc,
@@ -243,9 +261,19 @@ trioseq_status trioseq_serve_poll(trioseq_server* srv, trioseq_result* out, size
  * result is consumed: it will not be returned by poll. */
 trioseq_status trioseq_serve_wait(trioseq_server* srv, uint64_t id, trioseq_result* out,
                                   int64_t timeout_ns);
+/* Statistics since create (both names are the same call). */
+trioseq_status trioseq_serve_stats_get(trioseq_server* srv, trioseq_serve_stats* st);
 trioseq_status trioseq_serve_get_stats(trioseq_server* srv, trioseq_serve_stats* st);
 /* Stops admission, finishes queued and in-flight work, frees everything. */
 trioseq_status trioseq_serve_destroy(trioseq_server* srv);
+
+/* Bound on every wait of a kernel for another wavefront (a split triplet's
+ * panels wait for their neighbours' faces), for launches and hipGraph
+ * captures made after the call; ns = 0 restores the default of 2 s. A wait
+ * that reaches it gives up: the run goes on and every score it produces for
+ * a split triplet is INT32_MIN (served requests fail with
+ * TRIOSEQ_ERR_DEVICE), never a wrong value. For tests of that failure path. */
+void trioseq_set_wait_limit(uint64_t ns);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char* trioseq_last_error(void);

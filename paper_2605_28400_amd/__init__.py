@@ -63,7 +63,7 @@ class TuneResult(ctypes.Structure):
 class ServeConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_device_bytes", ctypes.c_uint64),
                 ("max_len", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
-                ("max_batch", ctypes.c_uint32)]
+                ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32)]
 
 
 class Result(ctypes.Structure):
@@ -75,7 +75,8 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("failed", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
                 ("cells", ctypes.c_double), ("busy_s", ctypes.c_double),
-                ("p50_ns", ctypes.c_double), ("p99_ns", ctypes.c_double)]
+                ("p50_ns", ctypes.c_double), ("p99_ns", ctypes.c_double),
+                ("gcups", ctypes.c_double)]
 
 
 # Every symbol the C header declares (checked by the CPU test-suite).
@@ -83,8 +84,8 @@ EXPORTS = [
     "trioseq_scoring_simple", "trioseq_pack", "trioseq_packed_layout", "trioseq_score",
     "trioseq_score_batch", "trioseq_score_batch_packed", "trioseq_plan_create", "trioseq_plan_run", "trioseq_plan_get_info",
     "trioseq_plan_destroy", "trioseq_autotune", "trioseq_align", "trioseq_align_batch", "trioseq_serve_create", "trioseq_serve_submit", "trioseq_serve_poll",
-    "trioseq_serve_wait", "trioseq_serve_get_stats", "trioseq_serve_destroy",
-    "trioseq_last_error", "trioseq_version",
+    "trioseq_serve_wait", "trioseq_serve_stats_get", "trioseq_serve_get_stats", "trioseq_serve_destroy",
+    "trioseq_set_wait_limit", "trioseq_last_error", "trioseq_version",
 ]
 
 _lib = None
@@ -135,6 +136,10 @@ def lib() -> ctypes.CDLL:
     L.trioseq_serve_wait.restype = st
     L.trioseq_serve_get_stats.argtypes = [ctypes.c_void_p, P(ServeStats)]
     L.trioseq_serve_get_stats.restype = st
+    L.trioseq_serve_stats_get.argtypes = [ctypes.c_void_p, P(ServeStats)]
+    L.trioseq_serve_stats_get.restype = st
+    L.trioseq_set_wait_limit.argtypes = [ctypes.c_uint64]
+    L.trioseq_set_wait_limit.restype = None
     L.trioseq_serve_destroy.argtypes = [ctypes.c_void_p]
     L.trioseq_serve_destroy.restype = st
     L.trioseq_score_batch_packed.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -388,12 +393,19 @@ def version() -> str:
     return lib().trioseq_version().decode()
 
 
+def set_wait_limit(ns: int = 0) -> None:
+    """Bound on the kernels' waits for other wavefronts, for launches and graph
+    captures made afterwards (0 = the default of 2 s); see trioseq_set_wait_limit."""
+    lib().trioseq_set_wait_limit(int(ns))
+
+
 class Server:
     """Continuous-batching scoring server (one GPU, background device thread)."""
 
     def __init__(self, max_len: int = 2048, sc: Scoring | None = None, device: int = 0,
-                 max_queue: int = 0, max_batch: int = 0, max_device_bytes: int = 0):
-        cfg = ServeConfig(device, max_device_bytes, max_len, max_queue, max_batch)
+                 max_queue: int = 0, max_batch: int = 0, max_device_bytes: int = 0,
+                 max_inflight: int = 0):
+        cfg = ServeConfig(device, max_device_bytes, max_len, max_queue, max_batch, max_inflight)
         self._h = ctypes.c_void_p()
         check(lib().trioseq_serve_create(ctypes.byref(cfg), ctypes.byref(sc or _default_scoring()),
                                          ctypes.byref(self._h)))
@@ -424,7 +436,7 @@ class Server:
 
     def stats(self) -> dict:
         st = ServeStats()
-        check(lib().trioseq_serve_get_stats(self._h, ctypes.byref(st)))
+        check(lib().trioseq_serve_stats_get(self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in ServeStats._fields_}
 
     def close(self) -> None:

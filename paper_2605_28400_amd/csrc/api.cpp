@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <mutex>
@@ -196,8 +197,36 @@ SweepArgs make_sweep_args(const uint32_t* words, const TripletDesc* desc, const 
   a.red = red;
   a.plane = nullptr;
   a.plane_off = nullptr;
+  a.wait_ticks = wait_limit_ticks();
   a.sc = sc;
   return a;
+}
+
+// 2 s in ticks of the 100 MHz wall clock the kernels read.
+constexpr uint64_t kDefaultWaitTicks = 200000000ull;
+static std::atomic<uint64_t> g_wait_ticks{kDefaultWaitTicks};
+
+uint64_t wait_limit_ticks() { return g_wait_ticks.load(std::memory_order_relaxed); }
+
+// A private non-blocking stream per thread and device for the one-off work
+// of plan creation (clearing control words and face pools, uploading the job
+// tables, writing sentinel faces). Waiting for it stalls nothing else: no
+// caller stream and no other thread's work is synchronised. Never destroyed
+// (the HIP runtime may be gone at thread exit).
+hipError_t init_stream(int device, hipStream_t* out) {
+  static thread_local std::vector<hipStream_t>* streams = nullptr;
+  if (!streams) streams = new std::vector<hipStream_t>;
+  if ((int)streams->size() <= device) streams->resize(device + 1, nullptr);
+  hipStream_t& st = (*streams)[device];
+  if (!st) {
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      st = nullptr;
+      return e;
+    }
+  }
+  *out = st;
+  return hipSuccess;
 }
 
 trioseq_status device_props(DeviceProps* p) {
@@ -287,7 +316,11 @@ void trioseq_scoring_simple(trioseq_scoring* s, int32_t match, int32_t mismatch,
 
 const char* trioseq_last_error(void) { return g_err.c_str(); }
 
-const char* trioseq_version(void) { return "trioseq-mi355x 0.1 (gfx950)"; }
+const char* trioseq_version(void) { return "trioseq-mi355x 0.2 (gfx950)"; }
+
+void trioseq_set_wait_limit(uint64_t ns) {
+  g_wait_ticks.store(ns ? ns / 10 : kDefaultWaitTicks, std::memory_order_relaxed);
+}
 
 trioseq_status trioseq_pack(const char* seq, uint32_t len, uint32_t* words) {
   if (len && (!seq || !words)) return fail(TRIOSEQ_ERR_INVALID_ARG, "pack: NULL pointer");
@@ -445,6 +478,9 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
 // Autotuning cache: the best options per batch length profile.
 static std::mutex g_tune_mu;
 static std::vector<std::pair<std::string, trioseq_plan_options>> g_tuned;
+// Bumped whenever a tuned choice is remembered: cached plans made before it
+// are rebuilt so they take the choice.
+std::atomic<uint64_t> g_tune_epoch{0};
 
 static int log2_bucket(double v) {
   int b = 0;
@@ -480,6 +516,7 @@ void apply_tuned(const uint32_t* lens, size_t n, int kind, trioseq_plan_options*
 
 static void remember_tuned(const std::string& key, const trioseq_plan_options& o) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_epoch.fetch_add(1, std::memory_order_relaxed);
   for (auto& kv : g_tuned)
     if (kv.first == key) {
       kv.second = o;
@@ -634,21 +671,25 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
     return st;
   }
   hipError_t e;
+  // One-off initialisation runs on this thread's private stream, which is
+  // waited for alone before the plan is returned.
+  hipStream_t is = nullptr;
+  if ((e = init_stream(dp.device, &is)) != hipSuccess) return hip_bail(e, "hipStreamCreate");
   const uint64_t face_bytes = (uint64_t)p->grid * L.face_stride * sizeof(int);
   const uint64_t pool_bytes = L.pool_ints * sizeof(int);
   if ((e = hipMalloc((void**)&p->d_counter, 256)) != hipSuccess) return hip_bail(e, "hipMalloc");
   if ((e = hipMalloc((void**)&p->d_ctl, 256)) != hipSuccess) return hip_bail(e, "hipMalloc");
-  if ((e = hipMemset(p->d_ctl, 0, 256)) != hipSuccess) return hip_bail(e, "hipMemset");
+  if ((e = hipMemsetAsync(p->d_ctl, 0, 256, is)) != hipSuccess) return hip_bail(e, "hipMemset");
   if (nd) {
     if ((e = hipMalloc((void**)&p->d_desc, nd * sizeof(TripletDesc))) != hipSuccess)
       return hip_bail(e, "hipMalloc desc");
-    if ((e = hipMemcpy(p->d_desc, L.desc.data(), nd * sizeof(TripletDesc), hipMemcpyHostToDevice)) !=
-        hipSuccess)
+    if ((e = hipMemcpyAsync(p->d_desc, L.desc.data(), nd * sizeof(TripletDesc), hipMemcpyHostToDevice,
+                            is)) != hipSuccess)
       return hip_bail(e, "hipMemcpy desc");
     if ((e = hipMalloc((void**)&p->d_jobs, L.jobs.size() * sizeof(JobDesc))) != hipSuccess)
       return hip_bail(e, "hipMalloc jobs");
-    if ((e = hipMemcpy(p->d_jobs, L.jobs.data(), L.jobs.size() * sizeof(JobDesc),
-                       hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpyAsync(p->d_jobs, L.jobs.data(), L.jobs.size() * sizeof(JobDesc),
+                            hipMemcpyHostToDevice, is)) != hipSuccess)
       return hip_bail(e, "hipMemcpy jobs");
   }
   if (face_bytes && (e = hipMalloc((void**)&p->d_face, face_bytes)) != hipSuccess)
@@ -657,7 +698,7 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
     // Tagged faces start at tag 0, which no run uses, so nothing stale matches.
     if ((e = hipMalloc((void**)&p->d_pface, pool_bytes)) != hipSuccess)
       return hip_bail(e, "hipMalloc panel faces");
-    if ((e = hipMemset(p->d_pface, 0, pool_bytes)) != hipSuccess) return hip_bail(e, "hipMemset");
+    if ((e = hipMemsetAsync(p->d_pface, 0, pool_bytes, is)) != hipSuccess) return hip_bail(e, "hipMemset");
   }
   p->red_pairs = L.red_pairs();
   if (p->red_pairs &&
@@ -667,8 +708,7 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
   if ((e = hipMalloc((void**)&p->d_bnd, bnd_ints * sizeof(int))) != hipSuccess)
     return hip_bail(e, "hipMalloc boundary");
   p->bnd = carve_boundary(L.ks, L.lds_n0, p->d_bnd);
-  if ((e = launch_init_boundary(L.ks, p->bnd, nullptr)) != hipSuccess) return hip_bail(e, "boundary init");
-  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_bail(e, "boundary init");
+  if ((e = launch_init_boundary(L.ks, p->bnd, is)) != hipSuccess) return hip_bail(e, "boundary init");
   p->workspace_bytes = face_bytes + pool_bytes + bnd_ints * sizeof(int) +
                        (uint64_t)p->red_pairs * 2 * sizeof(int) +
                        nd * sizeof(TripletDesc) + L.jobs.size() * sizeof(JobDesc) + 512;
@@ -687,13 +727,17 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
         (e = hipMalloc((void**)&p->d_chunk_box, p->h_nchunk * 4)) != hipSuccess ||
         (e = hipMalloc((void**)&p->d_partial, p->h_nchunk * 8)) != hipSuccess ||
         (e = hipMalloc((void**)&p->d_hscores, 8)) != hipSuccess ||
-        (e = hipMemcpy(p->d_gather, hs.gather, sizeof hs.gather, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p->d_plane_off, plane_off, sizeof plane_off, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p->d_sdesc, &box, sizeof box, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemset(p->d_chunk_box, 0, p->h_nchunk * 4)) != hipSuccess)
+        (e = hipMemcpyAsync(p->d_gather, hs.gather, sizeof hs.gather, hipMemcpyHostToDevice, is)) != hipSuccess ||
+        (e = hipMemcpyAsync(p->d_plane_off, plane_off, sizeof plane_off, hipMemcpyHostToDevice, is)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(p->d_sdesc, &box, sizeof box, hipMemcpyHostToDevice, is)) != hipSuccess ||
+        (e = hipMemsetAsync(p->d_chunk_box, 0, p->h_nchunk * 4, is)) != hipSuccess)
       return hip_bail(e, "half-split buffers");
     p->workspace_bytes += 2 * pints * 4 + (uint64_t)hs.words * 4 + p->h_nchunk * 12 + 256;
+    // The host sources of these copies live until this function returns.
+    if ((e = hipStreamSynchronize(is)) != hipSuccess) return hip_bail(e, "plan init");
   }
+  if ((e = hipStreamSynchronize(is)) != hipSuccess) return hip_bail(e, "plan init");
   if (p->use_graph) {
     if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess)
       return hip_bail(e, "hipStreamCreate");
@@ -963,6 +1007,35 @@ static trioseq_status score_batch_packed_body(const uint32_t* d_words, const uin
   return trioseq_plan_run(c.plan, d_words, d_scores, hip_stream);
 }
 
+// trioseq_score / trioseq_score_batch: the plans (with their device inputs
+// and outputs) of this thread's last few batch shapes, reused when the same
+// lengths, scoring and device come again, so a repeated call only uploads,
+// launches and downloads. Plans whose workspace exceeds kHostCacheBytes are
+// freed after their call. Never freed at thread exit (the HIP runtime may
+// already be gone then).
+constexpr size_t kHostCacheEntries = 4;
+constexpr uint64_t kHostCacheBytes = 4ull << 30;
+struct HostBatchEntry {
+  int device = -1;
+  int engine = 0;
+  uint64_t epoch = 0;
+  std::vector<uint32_t> lens;
+  trioseq_scoring sc{};
+  trioseq_plan* plan = nullptr;
+  uint32_t* d_words = nullptr;
+  int32_t* d_scores = nullptr;
+  uint64_t last_use = 0;
+};
+static thread_local std::vector<HostBatchEntry>* g_host_cache = nullptr;
+static thread_local uint64_t g_host_clock = 0;
+
+static void host_entry_free(HostBatchEntry& c) {
+  (void)hipFree(c.d_words);
+  (void)hipFree(c.d_scores);
+  trioseq_plan_destroy(c.plan);
+  c = HostBatchEntry{};
+}
+
 static trioseq_status run_host_batch(const trioseq_triplet* t, size_t n, const trioseq_scoring* sc,
                                      int32_t* scores, hipStream_t s, int engine) {
   if (n && !scores) return fail(TRIOSEQ_ERR_INVALID_ARG, "scores is NULL");
@@ -973,25 +1046,62 @@ static trioseq_status run_host_batch(const trioseq_triplet* t, size_t n, const t
   st = pack_triplets(t, n, &lens, &offs, &words);
   if (st != TRIOSEQ_OK) return st;
   if (n == 0) return TRIOSEQ_OK;
-  trioseq_plan_options o{engine, 0, 0, 0, 0, 0};
-  trioseq_plan* plan = nullptr;
-  st = trioseq_plan_create(lens.data(), offs.data(), n, sc, &o, &plan);
-  if (st != TRIOSEQ_OK) return st;
-  uint32_t* d_words = nullptr;
-  int32_t* d_scores = nullptr;
-  hipError_t e = hipMalloc((void**)&d_words, words.size() * 4);
-  if (e == hipSuccess) e = hipMalloc((void**)&d_scores, n * 4);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_words, words.data(), words.size() * 4, hipMemcpyHostToDevice, s);
+  // A cached plan is only looked for on a working device; otherwise
+  // plan_create below validates the batch (before any device work) and
+  // reports the problem.
+  int device = -1;
+  if (hipGetDevice(&device) != hipSuccess) device = -1;
+  if (!g_host_cache) g_host_cache = new std::vector<HostBatchEntry>;
+  std::vector<HostBatchEntry>& cache = *g_host_cache;
+  const uint64_t epoch = g_tune_epoch.load(std::memory_order_relaxed);
+  HostBatchEntry* hit = nullptr;
+  for (HostBatchEntry& c : cache)
+    if (device >= 0 && c.plan && c.device == device && c.engine == engine && c.epoch == epoch && c.lens == lens &&
+        std::memcmp(&c.sc, sc, sizeof *sc) == 0)
+      hit = &c;
+  HostBatchEntry fresh;
+  if (!hit) {
+    trioseq_plan_options o{engine, 0, 0, 0, 0, 0};
+    st = trioseq_plan_create(lens.data(), offs.data(), n, sc, &o, &fresh.plan);
+    if (st != TRIOSEQ_OK) return st;
+    hipError_t e = hipMalloc((void**)&fresh.d_words, words.size() * 4);
+    if (e == hipSuccess) e = hipMalloc((void**)&fresh.d_scores, n * 4);
+    if (e != hipSuccess) {
+      host_entry_free(fresh);
+      return fail_hip(e, "batch: device buffers");
+    }
+    fresh.device = device;
+    fresh.engine = engine;
+    fresh.epoch = epoch;
+    fresh.lens = lens;
+    fresh.sc = *sc;
+    hit = &fresh;
+  }
+  hit->last_use = ++g_host_clock;
+  hipError_t e = hipMemcpyAsync(hit->d_words, words.data(), words.size() * 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
-    st = trioseq_plan_run(plan, d_words, d_scores, s);
+    st = trioseq_plan_run(hit->plan, hit->d_words, hit->d_scores, s);
     if (st == TRIOSEQ_OK) {
-      e = hipMemcpyAsync(scores, d_scores, n * 4, hipMemcpyDeviceToHost, s);
+      e = hipMemcpyAsync(scores, hit->d_scores, n * 4, hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
   }
-  (void)hipFree(d_words);
-  (void)hipFree(d_scores);
-  trioseq_plan_destroy(plan);
+  if (hit == &fresh) {
+    // Keep it when it is small enough, in place of the least recently used.
+    if (st == TRIOSEQ_OK && e == hipSuccess && fresh.plan->workspace_bytes <= kHostCacheBytes) {
+      if (cache.size() < kHostCacheEntries) {
+        cache.push_back(std::move(fresh));
+      } else {
+        HostBatchEntry* lru = &cache[0];
+        for (HostBatchEntry& c : cache)
+          if (c.last_use < lru->last_use) lru = &c;
+        host_entry_free(*lru);
+        *lru = std::move(fresh);
+      }
+    } else {
+      host_entry_free(fresh);
+    }
+  }
   if (st != TRIOSEQ_OK) return st;
   if (e != hipSuccess) return fail_hip(e, "batch");
   return TRIOSEQ_OK;

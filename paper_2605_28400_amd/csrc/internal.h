@@ -99,8 +99,14 @@ struct SweepArgs {
   // index j * (n2 + 1) + k. plane is null when no plane is wanted.
   int* plane;
   const uint64_t* plane_off;
+  // Bound on every wait for another wavefront, in ticks of the 100 MHz wall
+  // clock; past it the wave raises ctl[1] and goes on.
+  uint64_t wait_ticks;
   DevScoring sc;
 };
+
+// The wait bound new launches take (trioseq_set_wait_limit; 2 s by default).
+uint64_t wait_limit_ticks();
 
 struct KernelShape {
   int rj, rk;  // lane tile (rows x columns)

@@ -8,7 +8,7 @@
 // preallocated device arenas ("slots"), each with its own stream. Admission
 // takes requests first-come first-served while the round's device footprint
 // (packed words, per-wave workspace, panel faces) fits the slot. Up to
-// kSlots rounds are in flight at once, so requests that arrive while others
+// max_inflight rounds are in flight at once, so requests that arrive while others
 // run are launched immediately into a free slot and their waves take over
 // compute units as earlier rounds drain. Each score is written by the GPU
 // straight into mapped pinned host memory, so a request completes when its
@@ -34,7 +34,8 @@
 namespace trioseq {
 namespace {
 
-constexpr int kSlots = 4;
+constexpr uint32_t kDefaultInflight = 4;
+constexpr uint32_t kMaxInflight = 16;
 // Scores are bounded by 2^30 in magnitude, so this value marks "not yet".
 constexpr int32_t kPending = INT32_MIN + 1;
 
@@ -86,7 +87,7 @@ struct trioseq_server {
   KernelShape ks{4, 4, 2};
   int* d_bnd = nullptr;
   Boundary bnd{};
-  Slot slots[kSlots];
+  std::vector<Slot> slots;
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -342,6 +343,18 @@ static trioseq_status trioseq_serve_create_body(const trioseq_serve_config* cfg,
   s->cfg = *cfg;
   if (!s->cfg.max_queue) s->cfg.max_queue = 1u << 20;
   if (!s->cfg.max_batch) s->cfg.max_batch = 4096;
+  if (!s->cfg.max_inflight) s->cfg.max_inflight = kDefaultInflight;
+  if (s->cfg.max_inflight > kMaxInflight) {
+    delete s;
+    return fail(TRIOSEQ_ERR_INVALID_ARG,
+                "serve_create: max_inflight must be at most " + std::to_string(kMaxInflight));
+  }
+  try {
+    s->slots.resize(s->cfg.max_inflight);
+  } catch (...) {
+    delete s;
+    return fail(TRIOSEQ_ERR_NOMEM, "serve_create: host allocation");
+  }
   s->sc = *sc;
   s->dsc = make_dev_scoring(*sc);
   st = device_props(&s->dp);
@@ -350,7 +363,7 @@ static trioseq_status trioseq_serve_create_body(const trioseq_serve_config* cfg,
     return st;
   }
   uint64_t budget = cfg->max_device_bytes ? cfg->max_device_bytes : s->dp.hbm_bytes / 4;
-  const uint64_t per_slot = budget / kSlots / 256 * 256;
+  const uint64_t per_slot = budget / s->cfg.max_inflight / 256 * 256;
   // The largest single request must fit a slot on its own. A slot's tagged
   // region is sized for that request's panel faces; the rest of the slot
   // budget is its arena.
@@ -508,6 +521,7 @@ static trioseq_status trioseq_serve_get_stats_body(trioseq_server* s, trioseq_se
     st->busy_s = s->busy_s + (s->busy_since ? (double)(now_ns() - s->busy_since) * 1e-9 : 0.0);
     lat = s->lat_ns;
   }
+  st->gcups = st->busy_s > 0 ? st->cells / st->busy_s / 1e9 : 0.0;
   st->p50_ns = st->p99_ns = 0;
   if (!lat.empty()) {
     std::sort(lat.begin(), lat.end());
@@ -555,8 +569,12 @@ trioseq_status trioseq_serve_wait(trioseq_server* s, uint64_t id, trioseq_result
   return guarded([&] { return trioseq_serve_wait_body(s, id, out, timeout_ns); });
 }
 
-trioseq_status trioseq_serve_get_stats(trioseq_server* s, trioseq_serve_stats* st) {
+trioseq_status trioseq_serve_stats_get(trioseq_server* s, trioseq_serve_stats* st) {
   return guarded([&] { return trioseq_serve_get_stats_body(s, st); });
+}
+
+trioseq_status trioseq_serve_get_stats(trioseq_server* s, trioseq_serve_stats* st) {
+  return trioseq_serve_stats_get(s, st);
 }
 
 }  // extern "C"

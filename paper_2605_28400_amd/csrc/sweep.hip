@@ -110,7 +110,30 @@ struct PanelIO {
   int* right;         // this panel's right face (nullptr: not needed)
   int gen;            // run generation: wide-engine faces carry it as a tag
   int* err;           // set when a tag wait gave up (wide engine)
+  uint64_t wait_ticks;  // bound on each wait, in 100 MHz wall-clock ticks
 };
+
+// A wait that gave up: the run's error flag is raised, and the release fence
+// orders it before every store the wave issues afterwards. A panel that gave
+// up goes on with whatever its faces hold, so the flag must become visible
+// no later than the faces it writes from then on: a downstream panel that
+// consumes them (and the panel that publishes the score after it) then sees
+// the flag too.
+__device__ __forceinline__ void raise_error(int* err) {
+  if ((threadIdx.x & 63) == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
+// The score of a split triplet, published by its last panel once the sweep is
+// over: INT32_MIN if any wait of the run gave up. The acquire fence orders the
+// flag's load after the face loads that the panel's result depends on.
+__device__ __forceinline__ void publish_score(int32_t* so, int v, const int* err) {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const bool bad = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  // System scope: the score may live in mapped host memory (serving), where
+  // the host picks it up while the kernel is still running.
+  __hip_atomic_store(so, bad ? INT32_MIN : v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // Cross-wavefront hand-over in the wide engine. Every face entry is a
 // (value, tag) pair written by one 64-bit store, tag = the run's generation
@@ -139,11 +162,10 @@ __device__ __forceinline__ uint32_t opaque_zero() {
   return z;
 }
 
-// Bound on the wait for a stale chunk, in ticks of the 100 MHz wall clock.
-// Every wave leaves the loop: past the limit it raises the error flag and
-// proceeds (the score is then marked invalid), so a lost producer cannot
-// hang the GPU.
-constexpr uint64_t kWaitTicks = 200000000ull;  // 2 s
+// Every wait for another wavefront is bounded (PanelIO::wait_ticks, 2 s by
+// default, in ticks of the 100 MHz wall clock): past the limit the wave
+// raises the error flag and proceeds (the score is then marked invalid), so a
+// lost producer cannot hang the GPU.
 
 typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -395,8 +417,8 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
     const uint32_t probe_off = probe_top ? (uint32_t)((ps + kGJ - 1) * (int)ts)
                                          : (uint32_t)((ps + kGK - 1) * (int)RRB + 4 * 4 * ES);
     for (int attempt = 0;; ++attempt) {
-      if (wall_clock64() - t_start > kWaitTicks) {
-        if (lane == 0) __hip_atomic_store(io.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (wall_clock64() - t_start > io.wait_ticks) {
+        raise_error(io.err);
         break;
       }
       if (attempt >= 2) {
@@ -508,10 +530,10 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
             fin = lds_get(&split->in_ready);
             ffl = lds_get(&split->out_flushed);
             if (fin > t && ffl > t - kRing) break;
-            if (wall_clock64() - t_start > kWaitTicks) {
+            if (wall_clock64() - t_start > io.wait_ticks) {
               // Give up waiting for the rest of the job (the score is marked
               // invalid); the job still runs to its end.
-              if (lane == 0) __hip_atomic_store(io.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              raise_error(io.err);
               gave_up = true;
               break;
             }
@@ -736,9 +758,12 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
     run_chunk(c, cap_chunk, c + 1 < nchunks);
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-  // System scope: the score may live in mapped host memory (serving), where
-  // the host picks it up while the kernel is still running.
-  if (own)
+  // Whole-triplet jobs never wait, so their owner lane stores the score at
+  // once (system scope: the score may live in mapped host memory, where the
+  // host picks it up while the kernel is still running). The last panel of a
+  // split triplet leaves it in L.cap for the caller, which publishes it once
+  // it knows whether a wait of the run gave up.
+  if (MODE == kPlain && own)
     __hip_atomic_store(score_out, L.cap[rsel * RK + csel] + sc.gap2 * (n0 + n1 + n2),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   if (PLANE && plane) {
@@ -753,6 +778,16 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
       }
   }
   return KIND == kGlobal ? 0 : best;
+}
+
+// Global score of a split triplet from its last panel (pj, pk): the cell
+// (n0, n1, n2) that the panel's owner lane left in L.cap, unshifted.
+template <int RJ, int RK>
+__device__ __forceinline__ int split_score(const Lds<RJ, RK>& L, const TripletDesc& td, int pj, int pk,
+                                           int gap2) {
+  const int n0 = (int)td.len[0], n1 = (int)td.len[1], n2 = (int)td.len[2];
+  const int r = (n1 - pj * kGJ * RJ) % RJ, c = (n2 - pk * kGK * RK) % RK;
+  return L.cap[r * RK + c] + gap2 * (n0 + n1 + n2);
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -874,10 +909,10 @@ __device__ void panel_memory(SplitLds<RJ, RK>& S, const TripletDesc& td, const P
         if (__builtin_amdgcn_ballot_w64((bad >> b) & 1u) != 0) k = b;
       k = min(k, nb);
       if (gave_up) k = nb;
-      if (k <= 0 && stall_since && wall_clock64() - stall_since > kWaitTicks) {
+      if (k <= 0 && stall_since && wall_clock64() - stall_since > io.wait_ticks) {
         // Stop waiting for producers for the rest of the job (the score is
         // marked invalid) so that both waves finish it.
-        if (lane == 0) __hip_atomic_store(io.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        raise_error(io.err);
         gave_up = true;
         k = nb;
       }
@@ -996,6 +1031,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
     io.right = pk + 1 < PK ? base + fb_ints : nullptr;
     io.gen = gen;
     io.err = a.ctl + 1;
+    io.wait_ticks = a.wait_ticks;
     int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
     int best = 0;
     if (wave == 0)
@@ -1004,11 +1040,13 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
     else
       panel_memory<RJ, RK>(S, td, io);
     __syncthreads();
+    // Both waves are done: a wait of this job that gave up has raised the
+    // flag by now, and upstream panels raised theirs before writing the faces
+    // this job read.
     if (KIND != kGlobal) {
       if (wave == 0) finish_panel(a, jd.trip, td.out, PJ * PK, best);
-    } else if (so && threadIdx.x == 0 &&
-               __hip_atomic_load(io.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-      __hip_atomic_store(so, INT32_MIN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    } else if (so && threadIdx.x == 0) {
+      publish_score(so, split_score(S.L, td, pj, pk, a.sc.gap2), io.err);
     }
   }
 }
@@ -1064,6 +1102,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
           io.right = pk + 1 < PK ? fr : nullptr;
           io.gen = 0;
           io.err = nullptr;
+          io.wait_ticks = 0;
           int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
           best = max(best, sweep_panel<kPlain, KIND, PLANE, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk,
                                                                     io, so, plane, capt));
@@ -1084,14 +1123,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       io.right = pk + 1 < PK ? base + fb_ints : nullptr;
       io.gen = gen;
       io.err = a.ctl + 1;
+      io.wait_ticks = a.wait_ticks;
       int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
       const int best = sweep_panel<kTagged, KIND, PLANE, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk, io,
                                                                 so, plane, capt);
       if (KIND != kGlobal)
         finish_panel(a, jd.trip, td.out, PJ * PK, best);
-      else if (so && threadIdx.x == 0 &&
-               __hip_atomic_load(io.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-        __hip_atomic_store(so, INT32_MIN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      else if (so && threadIdx.x == 0)
+        publish_score(so, split_score(L, td, pj, pk, a.sc.gap2), io.err);
     }
   }
 }
