@@ -167,6 +167,19 @@ def served_stream(seed: int = 5, count: int = 100_000):
     return Workload(f"served_{count}_len64-2048", trips, seed), gaps
 
 
+def served_mix(seed: int = 8) -> Workload:
+    """A served round's mix: 60 requests with log-uniform ancestor lengths in
+    [64, 512] and four long ones (ancestors of 1536, 1792, 1900 and 2048
+    residues, the top of the served stream's range), in a seeded order;
+    substitution rates uniform in [0.02, 0.15]."""
+    rng = rng_for(seed)
+    lo, hi = math.log(64), math.log(512)
+    anc = [int(round(math.exp(rng.uniform(lo, hi)))) for _ in range(60)] + [1536, 1792, 1900, 2048]
+    order = rng.permutation(len(anc))
+    trips = [mutated_triplet(rng, anc[q], float(rng.uniform(0.02, 0.15))) for q in order]
+    return Workload("served_mix_64_len64-2048", trips, seed)
+
+
 def fuzz(seed: int, count: int, max_len: int, skewed: bool = True) -> list:
     """Random triplets with uniform lengths in [0, max_len] plus degenerate shapes."""
     rng = rng_for(seed)
@@ -193,4 +206,5 @@ WORKLOADS = {
     "single_1k": single_1k,
     "batch_8192": batch_8192,
     "single_4k": single_4k,
+    "served_mix": served_mix,
 }

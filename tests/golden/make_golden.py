@@ -6,6 +6,10 @@ its seed and the scoring, so the GPU tests can compare bit for bit without
 re-running multi-minute oracle computations.
 
     python tests/golden/make_golden.py single_128 single_1k batch_8192 single_4k
+    python tests/golden/make_golden.py single_1k:local batch_8192:semi-global
+
+A name may carry ":semi-global" or ":local" (paper, Section II: the
+semi-global and local variants); such scores go to <name>_<kind>.json.
 """
 import json
 import os
@@ -21,24 +25,30 @@ from paper_2605_28400_amd import synth  # noqa: E402
 OUT = os.path.dirname(os.path.abspath(__file__))
 
 
+KINDS = {"global": oracle.GLOBAL, "semi-global": oracle.SEMI_GLOBAL, "local": oracle.LOCAL}
+
+
 def main(names):
-    for name in names:
+    for arg in names:
+        name, _, kind = arg.partition(":")
+        kind = kind or "global"
         w = synth.WORKLOADS[name]()
         t0 = time.time()
         scores = oracle.score_batch(w.triplets, oracle.DEFAULT_SUB, oracle.DEFAULT_GAP,
-                                    threads=os.cpu_count())
+                                    threads=os.cpu_count(), kind=KINDS[kind])
         dt = time.time() - t0
         rec = {
-            "workload": w.name, "generator": name, "seed": w.seed,
+            "workload": w.name, "generator": name, "seed": w.seed, "kind": kind,
             "scoring": {"match": 1, "mismatch": -1, "gap": -2},
             "lengths": [[int(s.size) for s in t] for t in w.triplets],
             "cells": w.total_cells, "scores": [int(v) for v in scores],
             "oracle_seconds": round(dt, 2), "oracle_threads": os.cpu_count(),
         }
-        path = os.path.join(OUT, f"{name}.json")
+        fname = name if kind == "global" else f"{name}_{kind.replace('-', '')}"
+        path = os.path.join(OUT, f"{fname}.json")
         with open(path, "w") as f:
             json.dump(rec, f, separators=(",", ":"))
-        print(f"{name}: {len(scores)} scores, {w.total_cells:.3e} cells, {dt:.1f} s", flush=True)
+        print(f"{arg}: {len(scores)} scores, {w.total_cells:.3e} cells, {dt:.1f} s", flush=True)
 
 
 if __name__ == "__main__":

@@ -191,3 +191,54 @@ def test_missing_library_fails_loudly(tmp_path):
     out = subprocess.run([_sys.executable, "-c", code], capture_output=True, text=True,
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert "raised" in out.stdout and "absent.so" in out.stdout, out.stdout + out.stderr
+
+
+# The calls of the boundary as first proposed for this library (the paper's
+# problem statement: sequences, substitution scores, gap; Section II, and the
+# host pipeline of Section IV, Approach Overview).
+BOUNDARY = ["trioseq_scoring_simple", "trioseq_score", "trioseq_score_batch",
+            "trioseq_score_batch_packed", "trioseq_serve_create", "trioseq_serve_submit",
+            "trioseq_serve_poll", "trioseq_serve_wait", "trioseq_serve_stats_get",
+            "trioseq_serve_destroy", "trioseq_last_error"]
+
+
+def test_boundary_calls_declared_and_exported():
+    L = ts.lib()
+    names = declared_functions()
+    for name in BOUNDARY:
+        assert name in names and hasattr(L, name), name
+
+
+STRUCTS = {
+    "trioseq_scoring": ts.Scoring, "trioseq_triplet": ts.Triplet,
+    "trioseq_plan_options": ts.PlanOptions, "trioseq_plan_info": ts.PlanInfo,
+    "trioseq_tune_result": ts.TuneResult, "trioseq_serve_config": ts.ServeConfig,
+    "trioseq_result": ts.Result, "trioseq_serve_stats": ts.ServeStats,
+}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    # A C program built against include/trioseq.h prints every field's offset
+    # and each struct's size; the ctypes mirrors must agree.
+    import subprocess
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "trioseq.h"', "int main(void) {"]
+    for cname, cls in STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    want = {}
+    for line in out:
+        if line:
+            cname, field, value = line.split()
+            want[(cname, field)] = int(value)
+    for cname, cls in STRUCTS.items():
+        assert ctypes.sizeof(cls) == want[(cname, "size")], cname
+        for field, _ in cls._fields_:
+            assert getattr(cls, field).offset == want[(cname, field)], (cname, field)

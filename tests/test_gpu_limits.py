@@ -67,9 +67,10 @@ def test_two_sequences_past_the_sweep_limit(gpu):
     t = (synth.uniform_seq(rng, MAX + 3000), synth.uniform_seq(rng, MAX + 100),
          synth.uniform_seq(rng, 3))
     want = oracle.score(t)
-    say("lengths (19384, 16484, 3)")
-    got, info = run(gpu, [t], ts.scoring(), -1)
-    assert int(got[0]) == want
+    for engine in (-1, 0, 1):
+        say(f"lengths (19384, 16484, 3) engine {engine}")
+        got, info = run(gpu, [t], ts.scoring(), engine)
+        assert int(got[0]) == want
 
 
 def test_all_sequences_past_the_limit_rejected(gpu):

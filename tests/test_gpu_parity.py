@@ -156,13 +156,29 @@ def test_single_1k_matches_golden(torch_cuda):
         assert int(got[0]) == g["scores"][0]
 
 
+def test_single_1k_default_path_matches_golden(torch_cuda):
+    # The launch configuration the benchmark times for a lone triplet: default
+    # options (scored by halves), eager and graph replays, and the synchronous
+    # call twice (the second call reuses the cached plan).
+    g = load_golden("single_1k")
+    w = synth.single_1k()
+    say("single 1024x1000x1048 default options")
+    got, info = run_plan(torch_cuda, w.triplets, engine=-1)
+    assert info["engine"] == 1 and int(got[0]) == g["scores"][0]
+    outs, _ = run_plan(torch_cuda, w.triplets, engine=-1, use_graph=True, reps=3)
+    assert all(int(o[0]) == g["scores"][0] for o in outs)
+    assert ts.score(w.triplets[0]) == g["scores"][0]
+    assert ts.score(w.triplets[0]) == g["scores"][0]
+
+
 def test_single_4k_matches_golden(torch_cuda):
     g = load_golden("single_4k")
     w = synth.single_4k()
     assert [[int(s.size) for s in t] for t in w.triplets] == g["lengths"]
-    say("single 4096x4000x4150")
-    got, _ = run_plan(torch_cuda, w.triplets, engine=1)
-    assert int(got[0]) == g["scores"][0]
+    for engine in (-1, 1):
+        say(f"single 4096x4000x4150 engine={engine}")
+        got, _ = run_plan(torch_cuda, w.triplets, engine=engine)
+        assert int(got[0]) == g["scores"][0]
 
 
 def test_batch_8192_matches_golden(torch_cuda):
@@ -170,9 +186,10 @@ def test_batch_8192_matches_golden(torch_cuda):
     w = synth.batch_8192()
     assert [[int(s.size) for s in t] for t in w.triplets] == g["lengths"]
     want = np.asarray(g["scores"])
-    for use_graph in (False, True):
-        say(f"batch 8192 graph={use_graph}")
-        got, _ = run_plan(torch_cuda, w.triplets, engine=0, use_graph=use_graph)
+    for engine, tile, use_graph in ((0, (0, 0), False), (0, (0, 0), True), (-1, (0, 0), False),
+                                    (-1, (8, 4), True), (-1, (4, 8), False)):
+        say(f"batch 8192 engine={engine} tile={tile} graph={use_graph}")
+        got, _ = run_plan(torch_cuda, w.triplets, engine=engine, tile=tile, use_graph=use_graph)
         bad = np.flatnonzero(got != want)
         assert bad.size == 0, bad[:10]
 

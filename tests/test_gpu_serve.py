@@ -4,6 +4,8 @@ Every served score must equal the oracle's (and the score of the same triplet
 scored alone); requests that arrive while others run are admitted into new
 rounds that overlap on the device; bad requests fail alone.
 """
+import json
+import os
 import sys
 import threading
 import time
@@ -16,6 +18,8 @@ import paper_2605_28400_amd as ts
 from paper_2605_28400_amd import synth
 
 pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+INT32_MIN = -(1 << 31)
 
 
 def say(msg):
@@ -161,3 +165,90 @@ def test_served_kinds_equal_oracle(gpu, kind, okind):
     srv.close()
     assert np.array_equal(np.array(got), np.asarray(want)), \
         [(q, got[q], int(want[q])) for q in range(len(reqs)) if got[q] != want[q]][:5]
+
+
+def test_served_long_requests_equal_oracle(gpu):
+    # The top of the served stream's length range: four requests of 1500-2050
+    # residues (split into panel jobs) among 60 short ones, every score
+    # against the stored oracle scores, and alone (trioseq_score) = in the mix.
+    with open(os.path.join(GOLDEN, "served_mix.json")) as f:
+        g = json.load(f)
+    wl = synth.served_mix()
+    assert [[int(s.size) for s in t] for t in wl.triplets] == g["lengths"]
+    srv = ts.Server(max_len=2048, max_device_bytes=16 << 30)
+    say(f"serving {len(wl.triplets)} requests up to 2055 residues")
+    ids = []
+    for k, t in enumerate(wl.triplets):
+        ids.append(srv.submit(t))
+        if k % 16 == 15:
+            time.sleep(0.001)
+    got = []
+    for rid in ids:
+        r = srv.wait(rid, timeout_s=90)
+        assert r["status"] == 0, r
+        got.append(r["score"])
+    st = srv.stats()
+    srv.close()
+    assert got == g["scores"], [(q, got[q], g["scores"][q]) for q in range(len(got))
+                                if got[q] != g["scores"][q]][:5]
+    assert st["completed"] == len(ids) and st["gcups"] > 0
+    for q, t in enumerate(wl.triplets):
+        if max(s.size for s in t) > 1400:
+            say(f"alone: request {q}")
+            assert ts.score(t) == got[q]
+
+
+@pytest.mark.parametrize("inflight", [1, 8])
+def test_rounds_in_flight_setting(gpu, inflight):
+    reqs = mixed_requests(35, 160, lo=8, hi=200)
+    want = oracle.score_batch(reqs)
+    srv = ts.Server(max_len=256, max_batch=32, max_device_bytes=2 << 30, max_inflight=inflight)
+    say(f"max_inflight={inflight}")
+    ids = [srv.submit(t) for t in reqs]
+    got = [srv.wait(rid, timeout_s=60)["score"] for rid in ids]
+    st = srv.stats()
+    srv.close()
+    assert got == [int(v) for v in want]
+    assert st["rounds"] >= len(reqs) // 32
+
+
+def test_rounds_in_flight_limit_rejected(gpu):
+    with pytest.raises(ts.TrioseqError) as e:
+        ts.Server(max_len=64, max_inflight=17)
+    assert e.value.status == -1
+
+
+def test_wait_that_gives_up_never_reports_a_wrong_score(gpu):
+    # The kernels' waits for other wavefronts are bounded; a wait that gives up
+    # lets the run finish, and the score must then be INT32_MIN (a served
+    # request fails) rather than a value computed from stale faces. The
+    # condition is forced from the host with a wait bound of a few
+    # nanoseconds, so every wave still exits normally.
+    torch = gpu
+    rng = synth.rng_for(36)
+    t = synth.mutated_triplet(rng, 300, 0.1, lens=(300, 290, 310))
+    want = oracle.score(t)
+    lens, off, words = ts.pack_batch([t])
+    d_words = torch.from_numpy(words.view(np.int32)).cuda()
+    seen = []
+    ts.set_wait_limit(1)
+    try:
+        for engine in (1, -1):
+            plan = ts.Plan(lens, off, engine=engine)
+            for rep in range(3):
+                d_score = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+                say(f"forced give-up engine={engine} rep={rep}")
+                plan.run(d_words, d_score)
+                torch.cuda.synchronize()
+                seen.append(int(d_score.cpu()[0]))
+            plan.close()
+        srv = ts.Server(max_len=512, max_device_bytes=2 << 30)
+        served = srv.wait(srv.submit(t), timeout_s=60)
+        srv.close()
+    finally:
+        ts.set_wait_limit(0)
+    assert all(v in (INT32_MIN, want) for v in seen), seen
+    assert INT32_MIN in seen, seen
+    assert served["status"] != 0 or served["score"] == want, served
+    # Back at the default bound, the same triplet scores correctly.
+    assert ts.score(t) == want
