@@ -28,14 +28,10 @@ struct Box {
   uint64_t corner() const { return (uint64_t)lo[0] + lo[1] + lo[2]; }
 };
 
-// Device buffers freed on every exit path.
-struct DevBuf {
-  void* p = nullptr;
-  ~DevBuf() { (void)hipFree(p); }
-  hipError_t alloc(size_t bytes) { return hipMalloc(&p, std::max<size_t>(bytes, 4)); }
-  template <class T>
-  T* as() const { return (T*)p; }
-};
+template <class T>
+T* as(const PlaneWorkspace::Buf& b) {
+  return (T*)b.p;
+}
 
 // Appends codes[from, to) (reversed if asked), packed 16 per word from a
 // fresh word; returns its word offset.
@@ -55,6 +51,11 @@ trioseq_status hip_err(hipError_t e, const char* what) { return fail_hip(e, what
 
 // Leaves solved per k_leaf launch (bounds the column buffers of a launch).
 constexpr size_t kLeavesPerLaunch = 1 << 18;
+
+// Traceback workspace of this thread (see align_batch_impl).
+constexpr uint64_t kKeepBytes = 2ull << 30;
+thread_local PlaneWorkspace* g_ws = nullptr;
+thread_local int g_ws_device = -1;
 
 // One level: every box in `boxes` is split; its two children go to `next`.
 // root_score[t] is set when the box is triplet t's root (its first split).
@@ -106,20 +107,21 @@ trioseq_status split_level(PlaneWorkspace& ws, const std::vector<Box>& boxes,
   trioseq_status st = run_planes(ws, lens.data(), offs.data(), 2 * nb, words.data(), words.size(), sc,
                                  poff.data(), pints, s);
   if (st != TRIOSEQ_OK) return st;
-  DevBuf d_sd, d_out, d_chunk_box, d_partial;
   std::vector<int> out(3 * nb);
   const size_t nchunks = chunk_box.size();
   hipError_t e;
-  if ((e = d_sd.alloc(nb * sizeof(SplitDesc))) != hipSuccess || (e = d_out.alloc(3 * nb * 4)) != hipSuccess ||
-      (e = d_chunk_box.alloc(nchunks * 4)) != hipSuccess || (e = d_partial.alloc(nchunks * 8)) != hipSuccess ||
-      (e = hipMemcpyAsync(d_sd.p, sd.data(), nb * sizeof(SplitDesc), hipMemcpyHostToDevice, s)) !=
+  // The level's only wait: its split points are needed to lay out the next.
+  if ((e = ws_grow(ws.sd, nb * sizeof(SplitDesc), false, s)) != hipSuccess ||
+      (e = ws_grow(ws.split_out, 3 * nb * 4, false, s)) != hipSuccess ||
+      (e = ws_grow(ws.chunk_box, nchunks * 4, false, s)) != hipSuccess ||
+      (e = ws_grow(ws.partial, nchunks * 8, false, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(ws.sd.p, sd.data(), nb * sizeof(SplitDesc), hipMemcpyHostToDevice, s)) !=
           hipSuccess ||
-      (e = hipMemcpyAsync(d_chunk_box.p, chunk_box.data(), nchunks * 4, hipMemcpyHostToDevice, s)) !=
+      (e = hipMemcpyAsync(ws.chunk_box.p, chunk_box.data(), nchunks * 4, hipMemcpyHostToDevice, s)) !=
           hipSuccess ||
-      (e = launch_split((const int*)ws.plane.p, d_sd.as<SplitDesc>(), (uint32_t)nb,
-                        d_chunk_box.as<uint32_t>(), (uint32_t)nchunks, d_partial.as<int>(),
-                        d_out.as<int>(), s)) != hipSuccess ||
-      (e = hipMemcpyAsync(out.data(), d_out.p, 3 * nb * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = launch_split((const int*)ws.plane.p, as<SplitDesc>(ws.sd), (uint32_t)nb, as<uint32_t>(ws.chunk_box),
+                        (uint32_t)nchunks, as<int>(ws.partial), as<int>(ws.split_out), s)) != hipSuccess ||
+      (e = hipMemcpyAsync(out.data(), ws.split_out.p, 3 * nb * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
       (e = hipStreamSynchronize(s)) != hipSuccess)
     return hip_err(e, "align: split");
   for (size_t q = 0; q < nb; ++q) {
@@ -144,7 +146,7 @@ trioseq_status split_level(PlaneWorkspace& ws, const std::vector<Box>& boxes,
 }
 
 // Solves leaves[first, first + n) with k_leaf; columns and scores to host.
-trioseq_status solve_leaves(const std::vector<Box>& leaves, size_t first, size_t n,
+trioseq_status solve_leaves(PlaneWorkspace& ws, const std::vector<Box>& leaves, size_t first, size_t n,
                             const std::vector<uint32_t>& words, const std::vector<uint64_t>& soff,
                             const trioseq_scoring& sc, std::vector<LeafDesc>& ld,
                             std::vector<uint8_t>& cols, std::vector<uint32_t>& ncols,
@@ -165,31 +167,31 @@ trioseq_status solve_leaves(const std::vector<Box>& leaves, size_t first, size_t
   cols.assign(col_bytes, 0);
   ncols.assign(n, 0);
   lscore.assign(n, 0);
-  DevBuf d_words, d_leaves, d_cols, d_ncols, d_lscore;
   hipError_t e;
-  if ((e = d_words.alloc(words.size() * 4)) != hipSuccess ||
-      (e = d_leaves.alloc(n * sizeof(LeafDesc))) != hipSuccess ||
-      (e = d_cols.alloc(col_bytes)) != hipSuccess ||
-      (e = d_ncols.alloc(n * 4)) != hipSuccess || (e = d_lscore.alloc(n * 4)) != hipSuccess)
+  if ((e = ws_grow(ws.lwords, words.size() * 4, false, s)) != hipSuccess ||
+      (e = ws_grow(ws.leaves, n * sizeof(LeafDesc), false, s)) != hipSuccess ||
+      (e = ws_grow(ws.cols, col_bytes, false, s)) != hipSuccess ||
+      (e = ws_grow(ws.ncols, n * 4, false, s)) != hipSuccess ||
+      (e = ws_grow(ws.lscore, n * 4, false, s)) != hipSuccess)
     return hip_err(e, "align: leaf buffers");
   LeafArgs la;
-  la.words = d_words.as<uint32_t>();
-  la.leaves = d_leaves.as<LeafDesc>();
+  la.words = as<uint32_t>(ws.lwords);
+  la.leaves = as<LeafDesc>(ws.leaves);
   la.n = (uint32_t)n;
-  la.cols = d_cols.as<uint8_t>();
-  la.ncols = d_ncols.as<uint32_t>();
-  la.score = d_lscore.as<int32_t>();
+  la.cols = as<uint8_t>(ws.cols);
+  la.ncols = as<uint32_t>(ws.ncols);
+  la.score = as<int32_t>(ws.lscore);
   for (int x = 0; x < 4; ++x)
     for (int y = 0; y < 4; ++y) la.sub[4 * x + y] = sc.sub[x][y];
   la.gap = sc.gap;
-  if ((e = hipMemcpyAsync(d_words.p, words.data(), words.size() * 4, hipMemcpyHostToDevice, s)) !=
+  if ((e = hipMemcpyAsync(ws.lwords.p, words.data(), words.size() * 4, hipMemcpyHostToDevice, s)) !=
           hipSuccess ||
-      (e = hipMemcpyAsync(d_leaves.p, ld.data(), n * sizeof(LeafDesc), hipMemcpyHostToDevice, s)) !=
+      (e = hipMemcpyAsync(ws.leaves.p, ld.data(), n * sizeof(LeafDesc), hipMemcpyHostToDevice, s)) !=
           hipSuccess ||
       (e = launch_leaf(la, s)) != hipSuccess ||
-      (e = hipMemcpyAsync(cols.data(), d_cols.p, col_bytes, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-      (e = hipMemcpyAsync(ncols.data(), d_ncols.p, n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-      (e = hipMemcpyAsync(lscore.data(), d_lscore.p, n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(cols.data(), ws.cols.p, col_bytes, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(ncols.data(), ws.ncols.p, n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(lscore.data(), ws.lscore.p, n * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
       (e = hipStreamSynchronize(s)) != hipSuccess)
     return hip_err(e, "align: leaves");
   return TRIOSEQ_OK;
@@ -228,7 +230,25 @@ trioseq_status align_batch_impl(const trioseq_triplet* t, size_t n, const triose
   for (size_t u = 0; u < n; ++u) work.push_back(Box{(uint32_t)u, {0, 0, 0}, {t[u].len[0], t[u].len[1], t[u].len[2]}});
   std::vector<char> split_seen(n, 0);
   std::vector<int32_t> root_score(n, 0);
-  PlaneWorkspace ws;
+  // This thread's traceback workspace, kept from call to call (and from
+  // level to level) so that a repeated alignment allocates nothing; one
+  // grown past kKeepBytes is released when the call ends.
+  int device = 0;
+  TRIOSEQ_HIP(hipGetDevice(&device), "hipGetDevice");
+  if (!g_ws || g_ws_device != device) {
+    delete g_ws;  // the previous device's buffers (synchronous calls: idle)
+    g_ws = new PlaneWorkspace;
+    g_ws_device = device;
+  }
+  PlaneWorkspace& ws = *g_ws;
+  struct Release {
+    ~Release() {
+      if (g_ws && ws_bytes(*g_ws) > kKeepBytes) {
+        delete g_ws;
+        g_ws = nullptr;
+      }
+    }
+  } release;
   while (!work.empty()) {
     std::vector<Box> boxes, next;
     for (const Box& b : work) (b.cells() <= kLeafCells ? leaves : boxes).push_back(b);
@@ -257,7 +277,7 @@ trioseq_status align_batch_impl(const trioseq_triplet* t, size_t n, const triose
   std::vector<int32_t> lscore;
   for (size_t first = 0; first < leaves.size(); first += kLeavesPerLaunch) {
     const size_t cnt = std::min(kLeavesPerLaunch, leaves.size() - first);
-    trioseq_status st = solve_leaves(leaves, first, cnt, words, soff, sc, ld, cols, ncols, lscore, s);
+    trioseq_status st = solve_leaves(ws, leaves, first, cnt, words, soff, sc, ld, cols, ncols, lscore, s);
     if (st != TRIOSEQ_OK) return st;
     for (size_t q = 0; q < cnt; ++q) {
       const uint32_t u = leaves[first + q].trip;

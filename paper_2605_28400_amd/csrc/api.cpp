@@ -749,12 +749,22 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
 namespace trioseq {
 
 PlaneWorkspace::~PlaneWorkspace() {
-  for (Buf* b : {&ctl, &desc, &jobs, &face, &pool, &bnd, &red, &plane, &plane_off, &words, &scores})
+  for (Buf* b : {&ctl, &desc, &jobs, &face, &pool, &bnd, &red, &plane, &plane_off, &words, &scores, &sd,
+                 &split_out, &chunk_box, &partial, &lwords, &leaves, &cols, &ncols, &lscore})
     (void)hipFree(b->p);
 }
 
-// Makes b hold at least `bytes` (contents not kept). zero: clear a new buffer.
-static hipError_t ws_grow(PlaneWorkspace::Buf& b, uint64_t bytes, bool zero, hipStream_t s) {
+uint64_t ws_bytes(const PlaneWorkspace& ws) {
+  uint64_t t = 0;
+  for (const PlaneWorkspace::Buf* b :
+       {&ws.ctl, &ws.desc, &ws.jobs, &ws.face, &ws.pool, &ws.bnd, &ws.red, &ws.plane, &ws.plane_off,
+        &ws.words, &ws.scores, &ws.sd, &ws.split_out, &ws.chunk_box, &ws.partial, &ws.lwords, &ws.leaves,
+        &ws.cols, &ws.ncols, &ws.lscore})
+    t += b->bytes;
+  return t;
+}
+
+hipError_t ws_grow(PlaneWorkspace::Buf& b, uint64_t bytes, bool zero, hipStream_t s) {
   bytes = std::max<uint64_t>(bytes, 256);
   if (b.bytes >= bytes) return hipSuccess;
   hipError_t e = hipStreamSynchronize(s);  // the old buffer may still be in use

@@ -118,6 +118,8 @@ struct PlaneWorkspace {
     uint64_t bytes = 0;
   };
   Buf ctl, desc, jobs, face, pool, bnd, red, plane, plane_off, words, scores;
+  // Traceback levels: split descriptors and results, leaf tables and columns.
+  Buf sd, split_out, chunk_box, partial, lwords, leaves, cols, ncols, lscore;
   Boundary boundary{};
   uint32_t bnd_n0 = 0;
   bool have_props = false;
@@ -128,6 +130,11 @@ struct PlaneWorkspace {
   std::vector<JobDesc> h_jobs;
   ~PlaneWorkspace();
 };
+// Makes b hold at least `bytes` (contents not kept; a buffer in use is only
+// replaced after the stream drains). zero: clear a new buffer.
+hipError_t ws_grow(PlaneWorkspace::Buf& b, uint64_t bytes, bool zero, hipStream_t s);
+// Bytes the workspace holds on the device.
+uint64_t ws_bytes(const PlaneWorkspace& ws);
 // Lays out and sweeps n triplets (lens / word offsets on the host, words[0,
 // nwords) packed on the host), leaving the planes in ws.plane (device).
 trioseq_status run_planes(PlaneWorkspace& ws, const uint32_t* lens, const uint64_t* offs, size_t n,

@@ -175,8 +175,9 @@ def test_served_long_requests_equal_oracle(gpu):
         g = json.load(f)
     wl = synth.served_mix()
     assert [[int(s.size) for s in t] for t in wl.triplets] == g["lengths"]
-    srv = ts.Server(max_len=2048, max_device_bytes=16 << 30)
-    say(f"serving {len(wl.triplets)} requests up to 2055 residues")
+    longest = max(int(s.size) for t in wl.triplets for s in t)
+    srv = ts.Server(max_len=longest, max_device_bytes=40 << 30)
+    say(f"serving {len(wl.triplets)} requests up to {longest} residues")
     ids = []
     for k, t in enumerate(wl.triplets):
         ids.append(srv.submit(t))
