@@ -57,12 +57,12 @@ TRAFFIC = {
 
 def scoring_path(trips, kind: str, engine: int, tile: str) -> str:
     """Which kernels a plan runs: "halves" (a lone global triplet whose longest
-    sequence has at least 256 residues, automatic options: its two halves swept
+    sequence has at least 256 residues, automatic engine, 4x4 tiles: its two halves swept
     concurrently with the last-slice plane variant, then met), "split" (panel
     jobs), or "batch" (several triplets)."""
     if len(trips) != 1:
         return "batch"
-    if kind == "global" and engine == -1 and tile == "0x0" and max(s.size for s in trips[0]) >= 256:
+    if kind == "global" and engine == -1 and tile in ("0x0", "4x4") and max(s.size for s in trips[0]) >= 256:
         return "halves"
     return "split"
 

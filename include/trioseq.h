@@ -166,6 +166,22 @@ typedef struct trioseq_plan_options {
   int32_t grid;           /* wavefronts to launch; 0 = fill the device */
   int32_t use_graph;      /* 1 = capture the launch sequence in a hipGraph and replay it */
   int32_t waves_per_simd; /* register budget of the kernel: 4 or 2; 0 = default */
+  int32_t panel_group;    /* plans of panel jobs only: 1 = one panel per job, swept by
+                             a workgroup of one computing and one staging wave; 4 =
+                             strip jobs of four adjacent panels of one panel row,
+                             swept by a workgroup of four such wave pairs that pass
+                             the faces between the strip's panels in LDS (the
+                             computing waves on distinct SIMDs); 0 = default */
+  int32_t lane_exchange;  /* how the lanes of a wavefront pass tile edges to their
+                             neighbours: 1 = through per-wave LDS slot arrays; 2 =
+                             through ds_bpermute and DPP row shifts (no LDS round
+                             trip); 0 = default */
+  int32_t split_factor;   /* automatic engine: a triplet of a batch is split into panel
+                             jobs when its cells exceed split_factor times the batch's
+                             mean cells per wavefront (or 2.5e8); 0 = default (4) */
+  int32_t half_split_min; /* automatic engine, one global triplet: scored by two
+                             concurrent halves when its longest sequence has at least
+                             this many residues; -1 = never; 0 = default (256) */
 } trioseq_plan_options;
 
 typedef struct trioseq_plan_info {
@@ -203,14 +219,18 @@ typedef struct trioseq_tune_result {
   int32_t rejected;          /* configurations whose scores differed from the reference's */
 } trioseq_tune_result;
 
-/* Times every supported lane-tile / register-budget configuration on the
- * caller's batch (lens, word_off and d_words as for plans; reps timed runs
- * each, on hip_stream) and returns the fastest one whose scores equal the
- * reference configuration's, score for score (a candidate that differs is
- * rejected and never chosen). The choice is remembered for the process,
- * keyed by the batch's length profile (triplet count, largest length and
- * total cells, each bucketed by powers of two): later plan_create calls that
- * leave tile_rows, tile_cols and waves_per_simd at 0 use it. Synchronous. */
+/* Times candidate configurations on the caller's batch (lens, word_off and
+ * d_words as for plans; reps timed runs each, on hip_stream) and returns the
+ * fastest one whose scores equal the reference configuration's (the library
+ * defaults), score for score (a candidate that differs is rejected and never
+ * chosen). Candidates: every lane tile (panel shape) and register budget,
+ * the register lane exchange, split factors 2, 8 and 16, strip workgroups,
+ * and for one triplet half-split thresholds 128 and 512 and no half split.
+ * The choice is remembered for the process, keyed by the batch's length
+ * profile (triplet count, largest length and total cells, each bucketed by
+ * powers of two): later plan_create calls that leave tile_rows, tile_cols and
+ * waves_per_simd at 0 take all of its options that they leave at 0.
+ * Synchronous. */
 trioseq_status trioseq_autotune(const uint32_t* lens, const uint64_t* word_off, size_t n,
                                 const trioseq_scoring* sc, const uint32_t* d_words, int32_t reps,
                                 void* hip_stream, trioseq_tune_result* out);

@@ -44,7 +44,9 @@ class Triplet(ctypes.Structure):
 class PlanOptions(ctypes.Structure):
     _fields_ = [("engine", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("tile_cols", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+                ("panel_group", ctypes.c_int32), ("lane_exchange", ctypes.c_int32),
+                ("split_factor", ctypes.c_int32), ("half_split_min", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -98,6 +100,14 @@ def lib() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run paper_2605_28400_amd/build.py (hipcc, gfx950)")
+    # torch ships its own HIP runtime under the same soname: loaded first, it
+    # also serves this library, so the process holds one runtime (loading the
+    # library first would bring in a second one, and the first of the two to
+    # open the device would own it).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     st = ctypes.c_int
@@ -329,14 +339,17 @@ class Plan:
     """Device-resident batch plan: ``run`` enqueues one scoring pass on a stream."""
 
     def __init__(self, lens, word_off=None, sc: Scoring | None = None, engine: int = -1,
-                 tile=(0, 0), grid: int = 0, use_graph: bool = False, waves_per_simd: int = 0):
+                 tile=(0, 0), grid: int = 0, use_graph: bool = False, waves_per_simd: int = 0,
+                 panel_group: int = 0, lane_exchange: int = 0, split_factor: int = 0,
+                 half_split_min: int = 0):
         self.lens = np.ascontiguousarray(lens, dtype=np.uint32)
         self.n = self.lens.size // 3
         off_p = None
         if word_off is not None:
             self._off = np.ascontiguousarray(word_off, dtype=np.uint64)
             off_p = self._off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
-        opts = PlanOptions(engine, tile[0], tile[1], grid, 1 if use_graph else 0, waves_per_simd)
+        opts = PlanOptions(engine, tile[0], tile[1], grid, 1 if use_graph else 0, waves_per_simd,
+                           panel_group, lane_exchange, split_factor, half_split_min)
         self._h = ctypes.c_void_p()
         check(lib().trioseq_plan_create(self.lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                         off_p, self.n, ctypes.byref(sc or _default_scoring()),

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -283,6 +285,8 @@ struct trioseq_plan {
   hipGraphExec_t gexec = nullptr;
   const uint32_t* g_words = nullptr;
   int32_t* g_scores = nullptr;
+  // Device buffers carved from a caller's region (not owned).
+  bool borrowed = false;
 };
 
 static void plan_free(trioseq_plan* p) {
@@ -290,6 +294,11 @@ static void plan_free(trioseq_plan* p) {
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->borrowed) {
+    // Carved from a caller's region: nothing to free on the device.
+    delete p;
+    return;
+  }
   (void)hipFree(p->d_desc);
   (void)hipFree(p->d_jobs);
   (void)hipFree(p->d_counter);
@@ -367,8 +376,17 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   if (st != TRIOSEQ_OK) return st;
   if (o.engine < -1 || o.engine > 1) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: bad engine");
   if (o.grid < 0) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: negative grid");
+  if (o.split_factor < 0) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: negative split_factor");
+  if (o.half_split_min < -1) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: bad half_split_min");
+  if (o.panel_group != 0 && o.panel_group != 1 && o.panel_group != 4)
+    return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: panel_group must be 0, 1 or 4");
+  static_assert(kStripPanels == 4, "panel_group option values");
   KernelShape ks{o.tile_rows ? o.tile_rows : 4, o.tile_cols ? o.tile_cols : 4,
                  o.waves_per_simd ? o.waves_per_simd : 2};
+  ks.group = o.panel_group ? o.panel_group : kDefaultPanelGroup;
+  if (o.lane_exchange < 0 || o.lane_exchange > 2)
+    return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: lane_exchange must be 0, 1 or 2");
+  ks.xch = o.lane_exchange ? o.lane_exchange - 1 : kDefaultLaneExchange;
   if (!shape_supported(ks, sc.kind))
     return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: unsupported tile shape for this scoring kind");
   std::vector<uint64_t> offs;
@@ -406,8 +424,9 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   for (size_t t = 0; t < n; ++t) {
     const uint32_t* l = lens + 3 * t;
     const double c = (double)l[0] * l[1] * l[2];
+    const double factor = o.split_factor > 0 ? (double)o.split_factor : kSplitFactor;
     const bool sp = o.engine == 1 ||
-                    (o.engine == -1 && (n == 1 || c >= kSplitCells || c > kSplitFactor * per_wave));
+                    (o.engine == -1 && (n == 1 || c >= kSplitCells || c > factor * per_wave));
     // Plane runs keep the caller's axes: the plane is the last slice of S0.
     AxisChoice ax = planes ? AxisChoice{{0, 1, 2}} : sp ? choose_axes_wide(l) : choose_axes_batch(l, ks);
     TripletDesc& d = L->desc[t];
@@ -433,6 +452,8 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   }
   L->engine = n_split == 0 ? 0 : (n_split == (int)n ? 1 : 2);
   L->modes = n_split == 0 ? 1 : (n_split == (int)n ? 2 : 3);
+  // Strip workgroups serve plans of panel jobs only.
+  if (L->modes != 2) ks.group = 1;
   // Whole-triplet-only plans fit four waves per SIMD without much spilling
   // on 4x4 tiles; panel jobs carry tag registers and use the two-wave budget.
   if (!planes && !o.waves_per_simd && L->modes == 1 && ks.rj * ks.rk <= 16) {
@@ -462,13 +483,19 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   uint32_t diagonals = 0;
   for (size_t t : idx)
     if (split[t]) diagonals = std::max(diagonals, L->desc[t].len[1] / H + L->desc[t].len[2] / W + 1);
+  // With strip workgroups a job is a strip of kStripPanels panels of one
+  // panel row (panel = its first panel), ordered by the diagonal of (panel
+  // row, strip index): its top faces come from the strip above, its left face
+  // from the strip before it in the row.
+  const uint32_t sw = ks.group > 1 ? (uint32_t)kStripPanels : 1u;
   for (uint32_t d = 0; d < diagonals; ++d)
     for (size_t t : idx) {
       if (!split[t]) continue;
       const uint32_t PJ = L->desc[t].len[1] / H + 1, PK = L->desc[t].len[2] / W + 1;
-      if (d + 1 >= PJ + PK) continue;
-      for (uint32_t pj = (d >= PK ? d - PK + 1 : 0); pj <= std::min(d, PJ - 1); ++pj)
-        L->jobs.push_back(JobDesc{(uint32_t)t, pj * PK + (d - pj)});
+      const uint32_t NS = (PK + sw - 1) / sw;  // strips (or panels) per panel row
+      if (d + 1 >= PJ + NS) continue;
+      for (uint32_t pj = (d >= NS ? d - NS + 1 : 0); pj <= std::min(d, PJ - 1); ++pj)
+        L->jobs.push_back(JobDesc{(uint32_t)t, pj * PK + (d - pj) * sw});
     }
   for (size_t t : idx)
     if (!split[t]) L->jobs.push_back(JobDesc{(uint32_t)t, kWholeTriplet});
@@ -511,6 +538,10 @@ void apply_tuned(const uint32_t* lens, size_t n, int kind, trioseq_plan_options*
       o->tile_rows = kv.second.tile_rows;
       o->tile_cols = kv.second.tile_cols;
       o->waves_per_simd = kv.second.waves_per_simd;
+      if (!o->panel_group) o->panel_group = kv.second.panel_group;
+      if (!o->lane_exchange) o->lane_exchange = kv.second.lane_exchange;
+      if (!o->split_factor) o->split_factor = kv.second.split_factor;
+      if (!o->half_split_min) o->half_split_min = kv.second.half_split_min;
     }
 }
 
@@ -533,6 +564,7 @@ static std::vector<std::pair<std::string, int>> g_occ;
 static hipError_t cached_occupancy(const Layout& L, int device, int* w) {
   const std::string key = std::to_string(device) + "/" + std::to_string(L.ks.rj) + "x" +
                           std::to_string(L.ks.rk) + "/" + std::to_string(L.ks.wpe) + "/" +
+                          std::to_string(L.ks.group) + "/" + std::to_string(L.ks.xch) + "/" +
                           std::to_string(L.modes) + "/" + std::to_string(L.kind) + "/" +
                           std::to_string((int)L.planes) + "/" + std::to_string(shift_lds_bytes(L.lds_n0));
   {
@@ -544,6 +576,12 @@ static hipError_t cached_occupancy(const Layout& L, int device, int* w) {
       }
   }
   hipError_t e = sweep_occupancy(L.ks, L.modes, L.kind, L.planes, L.lds_n0, w);
+  if (e == hipSuccess && L.modes == 2 && L.ks.group > 1) {
+    // A strip workgroup's 2 * kStripPanels waves fill 4 SIMDs x (waves per
+    // SIMD) slots of a compute unit; the runtime's figure for these
+    // workgroups was measured above that (launches beyond it only queue).
+    *w = std::max(1, std::min(*w, 4 * L.ks.wpe / (2 * kStripPanels)));
+  }
   if (e == hipSuccess) {
     std::lock_guard<std::mutex> lk(g_occ_mu);
     g_occ.emplace_back(key, *w);
@@ -558,7 +596,9 @@ trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested
   int g = requested ? requested : dp.cus * std::max(1, w);
   g = (int)std::min<size_t>((size_t)g, std::max<size_t>(L.jobs.size(), 1));
   *grid = g;
-  *waves_per_cu = w;
+  // Waves per compute unit: workgroups of 1 (whole triplets), 2 (panel jobs)
+  // or 2 * kStripPanels (strip jobs) waves.
+  *waves_per_cu = w * (L.modes == 1 || L.modes == 3 ? 1 : L.ks.group > 1 ? 2 * kStripPanels : 2);
   return TRIOSEQ_OK;
 }
 
@@ -581,12 +621,15 @@ struct HalfSplit {
   uint32_t rows = 0, cols = 0;
 };
 
-static bool half_split_layout(const uint32_t* lens, const uint64_t* word_off, HalfSplit* h) {
+static bool half_split_layout(const uint32_t* lens, const uint64_t* word_off, int32_t min_len,
+                              HalfSplit* h) {
   int ax = 0;
   for (int q = 1; q < 3; ++q)
     if (lens[q] > lens[ax]) ax = q;
   const uint32_t na = lens[ax];
-  if (na < kHalfSplitMin || (na + 1) / 2 > (uint32_t)kMaxSweepLen) return false;
+  if (min_len < 0) return false;
+  const uint32_t lo = min_len ? (uint32_t)std::max(min_len, 2) : kHalfSplitMin;
+  if (na < lo || (na + 1) / 2 > (uint32_t)kMaxSweepLen) return false;
   const int r = ax == 0 ? 1 : 0, c = ax == 2 ? 1 : 2;
   const uint32_t mid = na / 2;
   uint64_t src[3];
@@ -617,12 +660,17 @@ static bool half_split_layout(const uint32_t* lens, const uint64_t* word_off, Ha
 
 static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* word_off, size_t n,
                                        const trioseq_scoring* scp, const trioseq_plan_options* opts,
-                                       trioseq_plan** out) {
+                                       trioseq_plan** out, const PlanMemory* mem = nullptr) {
   if (!out) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: plan output is NULL");
   if (!scp) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan_create: scoring is NULL");
   trioseq_plan_options o{-1, 0, 0, 0, 0, 0};
   if (opts) o = *opts;
-  const bool defaults = o.engine == -1 && !o.tile_rows && !o.tile_cols && !o.waves_per_simd && !o.grid;
+  // A lone global triplet is scored by halves under the automatic engine and
+  // grid when the options leave the tile at (or set it to) the plane
+  // kernels' 4 x 4 at two waves per SIMD.
+  const bool defaults = o.engine == -1 && !o.grid && (o.tile_rows == 0 || o.tile_rows == 4) &&
+                        (o.tile_cols == 0 || o.tile_cols == 4) &&
+                        (o.waves_per_simd == 0 || o.waves_per_simd == 2);
   if (!o.tile_rows && !o.tile_cols && !o.waves_per_simd && lens) apply_tuned(lens, n, scp->kind, &o);
   // Inputs are validated (by the layout) before the device is touched; the
   // layout is redone if the device's size changes the split rule's hint.
@@ -632,8 +680,9 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
   if (st != TRIOSEQ_OK) return st;
   // A lone global triplet under the automatic options is scored by halves.
   HalfSplit hs;
-  const bool half = n == 1 && defaults && scp->kind == kGlobal && half_split_layout(lens, word_off, &hs);
-  const trioseq_plan_options ho{-1, 4, 4, 0, 0, 2};  // the plane kernels' shape
+  const bool half = n == 1 && defaults && scp->kind == kGlobal &&
+                    half_split_layout(lens, word_off, o.half_split_min, &hs);
+  const trioseq_plan_options ho{-1, 4, 4, 0, 0, 2, o.panel_group, o.lane_exchange};  // the plane kernels' shape
   DeviceProps dp;
   st = device_props(&dp);
   if (st != TRIOSEQ_OK) return st;
@@ -641,6 +690,13 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
     hint = dp.cus * kWavesPerCuHint;
     st = half ? build_layout(hs.lens, hs.offs, 2, *scp, ho, hint, &L, true)
               : build_layout(lens, word_off, n, *scp, o, hint, &L);
+    if (st != TRIOSEQ_OK) return st;
+  }
+  // A batch carved from a region whose pool cannot hold its split triplets'
+  // faces sweeps every triplet whole instead (same scores, no face pool).
+  if (mem && !half && n > 1 && o.engine == -1 && L.pool_ints * sizeof(int) > mem->pool_bytes) {
+    o.engine = 0;
+    st = build_layout(lens, word_off, n, *scp, o, hint, &L);
     if (st != TRIOSEQ_OK) return st;
   }
   const size_t nd = L.desc.size();  // triplets the kernels see
@@ -657,7 +713,7 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
   p->njobs = (uint32_t)L.jobs.size();
   p->sc = make_dev_scoring(*scp);
   p->cells = L.cells;
-  p->use_graph = o.use_graph != 0;
+  p->use_graph = o.use_graph != 0 && !mem;
   p->face_stride = L.face_stride;
   auto hip_bail = [&](hipError_t e, const char* what) {
     fail_hip(e, what);
@@ -672,44 +728,82 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
   }
   hipError_t e;
   // One-off initialisation runs on this thread's private stream, which is
-  // waited for alone before the plan is returned.
+  // waited for alone before the plan is returned (or, for a plan carved from
+  // a caller's region, on the caller's stream).
   hipStream_t is = nullptr;
-  if ((e = init_stream(dp.device, &is)) != hipSuccess) return hip_bail(e, "hipStreamCreate");
-  const uint64_t face_bytes = (uint64_t)p->grid * L.face_stride * sizeof(int);
+  if (mem) {
+    is = mem->stream;
+  } else if ((e = init_stream(dp.device, &is)) != hipSuccess) {
+    return hip_bail(e, "hipStreamCreate");
+  }
+  // Device buffers: hipMalloc'd and owned by the plan, or carved in order
+  // from the region's plain part (256-byte aligned); what is carved is never
+  // freed.
+  p->borrowed = mem != nullptr;
+  uint64_t carved = 0;
+  auto dalloc = [&](void** dst, uint64_t bytes) -> hipError_t {
+    if (!mem) return hipMalloc(dst, bytes);
+    const uint64_t at = (carved + 255) & ~255ull;
+    if (at + bytes > mem->plain_bytes) return hipErrorOutOfMemory;
+    *dst = mem->plain + at;
+    carved = at + bytes;
+    return hipSuccess;
+  };
+  auto too_large = [&](const std::string& what) {
+    plan_free(p);
+    return fail(TRIOSEQ_ERR_TOO_LARGE, "allocation-free scoring: " + what);
+  };
+  auto region_fail = [&](hipError_t e2, const char* what) {
+    if (mem && e2 == hipErrorOutOfMemory) return too_large(std::string(what) + " exceeds the scratch region");
+    return hip_bail(e2, what);
+  };
   const uint64_t pool_bytes = L.pool_ints * sizeof(int);
-  if ((e = hipMalloc((void**)&p->d_counter, 256)) != hipSuccess) return hip_bail(e, "hipMalloc");
-  if ((e = hipMalloc((void**)&p->d_ctl, 256)) != hipSuccess) return hip_bail(e, "hipMalloc");
-  if ((e = hipMemsetAsync(p->d_ctl, 0, 256, is)) != hipSuccess) return hip_bail(e, "hipMemset");
+  if (mem) {
+    // The generation word, error flag and queue head persist in the region
+    // (the generation only grows, so no stale tag ever looks current).
+    p->d_ctl = mem->ctl;
+    p->d_counter = mem->counter;
+  } else {
+    if ((e = hipMalloc((void**)&p->d_counter, 256)) != hipSuccess) return hip_bail(e, "hipMalloc");
+    if ((e = hipMalloc((void**)&p->d_ctl, 256)) != hipSuccess) return hip_bail(e, "hipMalloc");
+    if ((e = hipMemsetAsync(p->d_ctl, 0, 256, is)) != hipSuccess) return hip_bail(e, "hipMemset");
+  }
   if (nd) {
-    if ((e = hipMalloc((void**)&p->d_desc, nd * sizeof(TripletDesc))) != hipSuccess)
-      return hip_bail(e, "hipMalloc desc");
+    if ((e = dalloc((void**)&p->d_desc, nd * sizeof(TripletDesc))) != hipSuccess)
+      return region_fail(e, "triplet table");
     if ((e = hipMemcpyAsync(p->d_desc, L.desc.data(), nd * sizeof(TripletDesc), hipMemcpyHostToDevice,
                             is)) != hipSuccess)
       return hip_bail(e, "hipMemcpy desc");
-    if ((e = hipMalloc((void**)&p->d_jobs, L.jobs.size() * sizeof(JobDesc))) != hipSuccess)
-      return hip_bail(e, "hipMalloc jobs");
+    if ((e = dalloc((void**)&p->d_jobs, L.jobs.size() * sizeof(JobDesc))) != hipSuccess)
+      return region_fail(e, "job table");
     if ((e = hipMemcpyAsync(p->d_jobs, L.jobs.data(), L.jobs.size() * sizeof(JobDesc),
                             hipMemcpyHostToDevice, is)) != hipSuccess)
       return hip_bail(e, "hipMemcpy jobs");
   }
-  if (face_bytes && (e = hipMalloc((void**)&p->d_face, face_bytes)) != hipSuccess)
-    return hip_bail(e, "hipMalloc face workspace");
   if (pool_bytes) {
-    // Tagged faces start at tag 0, which no run uses, so nothing stale matches.
-    if ((e = hipMalloc((void**)&p->d_pface, pool_bytes)) != hipSuccess)
-      return hip_bail(e, "hipMalloc panel faces");
-    if ((e = hipMemsetAsync(p->d_pface, 0, pool_bytes, is)) != hipSuccess) return hip_bail(e, "hipMemset");
+    if (mem) {
+      // The region's pool part only ever holds (value, tag) pairs at even
+      // offsets from its fixed base, or the zeros it started with.
+      if (pool_bytes > mem->pool_bytes)
+        return too_large("panel faces of split triplets exceed the scratch array's face pool");
+      p->d_pface = mem->pool;
+    } else {
+      // Tagged faces start at tag 0, which no run uses, so nothing stale matches.
+      if ((e = hipMalloc((void**)&p->d_pface, pool_bytes)) != hipSuccess)
+        return hip_bail(e, "hipMalloc panel faces");
+      if ((e = hipMemsetAsync(p->d_pface, 0, pool_bytes, is)) != hipSuccess) return hip_bail(e, "hipMemset");
+    }
   }
   p->red_pairs = L.red_pairs();
   if (p->red_pairs &&
-      (e = hipMalloc((void**)&p->d_red, (uint64_t)p->red_pairs * 2 * sizeof(int))) != hipSuccess)
-    return hip_bail(e, "hipMalloc reduction pairs");
+      (e = dalloc((void**)&p->d_red, (uint64_t)p->red_pairs * 2 * sizeof(int))) != hipSuccess)
+    return region_fail(e, "reduction pairs");
   const uint64_t bnd_ints = boundary_ints(L.ks, L.lds_n0);
-  if ((e = hipMalloc((void**)&p->d_bnd, bnd_ints * sizeof(int))) != hipSuccess)
-    return hip_bail(e, "hipMalloc boundary");
+  if ((e = dalloc((void**)&p->d_bnd, bnd_ints * sizeof(int))) != hipSuccess)
+    return region_fail(e, "sentinel faces");
   p->bnd = carve_boundary(L.ks, L.lds_n0, p->d_bnd);
   if ((e = launch_init_boundary(L.ks, p->bnd, is)) != hipSuccess) return hip_bail(e, "boundary init");
-  p->workspace_bytes = face_bytes + pool_bytes + bnd_ints * sizeof(int) +
+  p->workspace_bytes = pool_bytes + bnd_ints * sizeof(int) +
                        (uint64_t)p->red_pairs * 2 * sizeof(int) +
                        nd * sizeof(TripletDesc) + L.jobs.size() * sizeof(JobDesc) + 512;
   if (half) {
@@ -719,15 +813,16 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
     p->h_nchunk = (uint32_t)((pints + kSplitChunk - 1) / kSplitChunk);
     const uint64_t plane_off[2] = {0, pints};
     const SplitDesc box{0, pints, hs.rows, hs.cols, 0, p->h_nchunk};
-    if ((e = hipMalloc((void**)&p->d_hwords, std::max<uint64_t>(hs.words, 1) * 4)) != hipSuccess ||
-        (e = hipMalloc((void**)&p->d_gather, sizeof hs.gather)) != hipSuccess ||
-        (e = hipMalloc((void**)&p->d_plane, 2 * pints * 4)) != hipSuccess ||
-        (e = hipMalloc((void**)&p->d_plane_off, sizeof plane_off)) != hipSuccess ||
-        (e = hipMalloc((void**)&p->d_sdesc, sizeof box)) != hipSuccess ||
-        (e = hipMalloc((void**)&p->d_chunk_box, p->h_nchunk * 4)) != hipSuccess ||
-        (e = hipMalloc((void**)&p->d_partial, p->h_nchunk * 8)) != hipSuccess ||
-        (e = hipMalloc((void**)&p->d_hscores, 8)) != hipSuccess ||
-        (e = hipMemcpyAsync(p->d_gather, hs.gather, sizeof hs.gather, hipMemcpyHostToDevice, is)) != hipSuccess ||
+    if ((e = dalloc((void**)&p->d_hwords, std::max<uint64_t>(hs.words, 1) * 4)) != hipSuccess ||
+        (e = dalloc((void**)&p->d_gather, sizeof hs.gather)) != hipSuccess ||
+        (e = dalloc((void**)&p->d_plane, 2 * pints * 4)) != hipSuccess ||
+        (e = dalloc((void**)&p->d_plane_off, sizeof plane_off)) != hipSuccess ||
+        (e = dalloc((void**)&p->d_sdesc, sizeof box)) != hipSuccess ||
+        (e = dalloc((void**)&p->d_chunk_box, p->h_nchunk * 4)) != hipSuccess ||
+        (e = dalloc((void**)&p->d_partial, p->h_nchunk * 8)) != hipSuccess ||
+        (e = dalloc((void**)&p->d_hscores, 8)) != hipSuccess)
+      return region_fail(e, "half-split buffers");
+    if ((e = hipMemcpyAsync(p->d_gather, hs.gather, sizeof hs.gather, hipMemcpyHostToDevice, is)) != hipSuccess ||
         (e = hipMemcpyAsync(p->d_plane_off, plane_off, sizeof plane_off, hipMemcpyHostToDevice, is)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(p->d_sdesc, &box, sizeof box, hipMemcpyHostToDevice, is)) != hipSuccess ||
@@ -736,6 +831,21 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
     p->workspace_bytes += 2 * pints * 4 + (uint64_t)hs.words * 4 + p->h_nchunk * 12 + 256;
     // The host sources of these copies live until this function returns.
     if ((e = hipStreamSynchronize(is)) != hipSuccess) return hip_bail(e, "plan init");
+  }
+  // The whole-triplet workspace comes last: a carved plan launches no more
+  // waves than the rest of the region holds workspaces for.
+  if (L.face_stride) {
+    const uint64_t per_wave = L.face_stride * sizeof(int);
+    if (mem) {
+      const uint64_t at = (carved + 255) & ~255ull;
+      const uint64_t fit = at < mem->plain_bytes ? (mem->plain_bytes - at) / per_wave : 0;
+      if (fit == 0) return too_large("the largest whole triplet's face workspace exceeds the scratch region");
+      p->grid = (int)std::min<uint64_t>((uint64_t)p->grid, fit);
+    }
+    const uint64_t face_bytes = (uint64_t)p->grid * per_wave;
+    if ((e = dalloc((void**)&p->d_face, face_bytes)) != hipSuccess)
+      return region_fail(e, "hipMalloc face workspace");
+    p->workspace_bytes += face_bytes;
   }
   if ((e = hipStreamSynchronize(is)) != hipSuccess) return hip_bail(e, "plan init");
   if (p->use_graph) {
@@ -1125,11 +1235,26 @@ static trioseq_status trioseq_autotune_body(const uint32_t* lens, const uint64_t
   if (n == 0) return fail(TRIOSEQ_ERR_INVALID_ARG, "autotune: empty batch");
   if (reps < 1) reps = 1;
   hipStream_t s = (hipStream_t)hip_stream;
-  // Candidates: the reference (library defaults) first, then every shape.
+  // Candidates: the reference (library defaults) first, then every lane tile
+  // (the panel a wave owns is 8 x 8 tiles) and register budget, the register
+  // lane exchange, other split factors (which triplets of a batch become
+  // panel jobs), strip workgroups, and for a lone triplet other half-split
+  // thresholds. Options a layout ignores are not tried.
   std::vector<trioseq_plan_options> cands;
-  cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 0});
-  const int shapes[][3] = {{4, 4, 4}, {4, 4, 2}, {8, 4, 2}, {4, 8, 2}};
+  cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 2});
+  const int shapes[][3] = {{4, 4, 4}, {8, 4, 2}, {4, 8, 2}};
   for (const auto& sh : shapes) cands.push_back(trioseq_plan_options{-1, sh[0], sh[1], 0, 0, sh[2]});
+  if (sc->kind == kGlobal) {
+    cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 2, 0, 2});
+    cands.push_back(trioseq_plan_options{-1, 8, 4, 0, 0, 2, 0, 2});
+  }
+  if (n > 1) {
+    for (int f : {2, 8, 16}) cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 2, 0, 0, f});
+  } else {
+    cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 2, 4});
+    if (sc->kind == kGlobal)
+      for (int h : {-1, 128, 512}) cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 2, 0, 0, 0, h});
+  }
   int32_t* d_ref = nullptr;
   int32_t* d_out = nullptr;
   TRIOSEQ_HIP(hipMalloc((void**)&d_ref, n * 4), "hipMalloc");
@@ -1190,6 +1315,10 @@ static trioseq_status trioseq_autotune_body(const uint32_t* lens, const uint64_t
       r.best.tile_cols = info.tile_cols;
       r.best.waves_per_simd = c == 0 ? 0 : cands[c].waves_per_simd;
     }
+    if (std::getenv("TRIOSEQ_TUNE_LOG"))
+      std::fprintf(stderr, "autotune: %dx%d wpe %d xch %d group %d split %d half %d: %.4f ms\n",
+                   info.tile_rows, info.tile_cols, cands[c].waves_per_simd, cands[c].lane_exchange,
+                   cands[c].panel_group, cands[c].split_factor, cands[c].half_split_min, ms);
   }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);

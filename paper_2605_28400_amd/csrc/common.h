@@ -96,6 +96,10 @@ struct Layout {
 trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
                             const trioseq_scoring& sc, const trioseq_plan_options& o, int waves_hint,
                             Layout* L, bool planes = false);
+// Pairs per workgroup of panel-only plans unless the options say otherwise.
+constexpr int kDefaultPanelGroup = 1;
+// Lane exchange (KernelShape::xch) unless the options say otherwise.
+constexpr int kDefaultLaneExchange = 0;
 // Resident wavefronts per compute unit assumed when sizing the split rule.
 constexpr int kWavesPerCuHint = 8;
 // Autotuning cache keyed by a batch's length profile and scoring kind.
@@ -105,6 +109,23 @@ void apply_tuned(const uint32_t* lens, size_t n, int kind, trioseq_plan_options*
 // Waves to launch for a layout on this device.
 trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested, int* grid,
                            int* waves_per_cu);
+
+// Device memory a plan is carved from instead of allocated (the
+// allocation-free entry point). plain: any data, carved in order; pool: only
+// ever (value, tag) face pairs at even int offsets from its fixed base, or the
+// zeros it started with, so a tag slot never holds a value; ctl (generation
+// word, error flag) and counter (queue head) persist from call to call, and
+// the generation only grows, so no stale tag ever looks current. stream:
+// where the plan's initialisation runs (the caller's).
+struct PlanMemory {
+  uint8_t* plain;
+  uint64_t plain_bytes;
+  int* pool;
+  uint64_t pool_bytes;
+  int* ctl;
+  int* counter;
+  hipStream_t stream;
+};
 
 // Traceback plane runs: sweeps of triplets that also write each triplet's
 // last slice (unshifted), triplet t at plane + plane_off[t]. The device

@@ -108,9 +108,18 @@ struct SweepArgs {
 // The wait bound new launches take (trioseq_set_wait_limit; 2 s by default).
 uint64_t wait_limit_ticks();
 
+// Panels of one strip job (strip workgroups: one compute and one memory wave
+// per panel, all in one workgroup).
+constexpr int kStripPanels = 4;
 struct KernelShape {
-  int rj, rk;  // lane tile (rows x columns)
-  int wpe;     // waves per SIMD the register budget is sized for
+  int rj, rk;     // lane tile (rows x columns)
+  int wpe;        // waves per SIMD the register budget is sized for
+  // Plans of panel jobs only: panels per workgroup, 1 (a job is one panel) or
+  // kStripPanels (a job is a strip of that many panels of one panel row).
+  int group = 1;
+  // Exchange between the lanes of a wavefront: 0 through per-wave LDS slot
+  // arrays, 1 through ds_bpermute and DPP row shifts.
+  int xch = 0;
 };
 
 // Launchers (sweep.hip).
@@ -122,11 +131,13 @@ hipError_t launch_prepare(int* ctl, int* counter, int* red, uint32_t nred, hipSt
 // The kernel variant follows a.sc.kind.
 hipError_t launch_sweep(const KernelShape& ks, int modes, const SweepArgs& a, int grid,
                         hipStream_t s);
-// plane: the variant that writes last-slice planes (traceback).
+// plane: the variant that writes last-slice planes (traceback). The figure is
+// workgroups per compute unit.
 hipError_t sweep_occupancy(const KernelShape& ks, int modes, int kind, bool plane, uint32_t lds_n0,
                            int* waves_per_cu);
-// Whether scoring kernels of this tile shape exist for this alignment kind.
-// Plane kernels exist for 4 x 4 tiles at two waves per SIMD, global kind.
+// Whether scoring kernels of this tile shape (and lane exchange) exist for
+// this alignment kind. Plane kernels exist for 4 x 4 tiles at two waves per
+// SIMD, global kind.
 bool shape_supported(const KernelShape& ks, int kind);
 
 // Traceback (traceback.hip). A split box: the forward and reversed planes

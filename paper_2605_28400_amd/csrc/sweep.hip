@@ -111,6 +111,14 @@ struct PanelIO {
   int gen;            // run generation: wide-engine faces carry it as a tag
   int* err;           // set when a tag wait gave up (wide engine)
   uint64_t wait_ticks;  // bound on each wait, in 100 MHz wall-clock ticks
+  // Strip workgroups (compute waves of adjacent panels in one workgroup):
+  // lds_left = the out rows of the left neighbour's compute wave, read in
+  // place of a staged left face, with its step counter prod_done; cons_done =
+  // the step counter of the right neighbour's compute wave, which reads this
+  // panel's right out rows in place (null: none in the workgroup).
+  const int* lds_left = nullptr;
+  const int* prod_done = nullptr;
+  const int* cons_done = nullptr;
 };
 
 // A wait that gave up: the run's error flag is raised, and the release fence
@@ -173,10 +181,10 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 // Per-slice lookup shifts: shb[i + kShiftPre] = 8 * code(S0[i-1]) for slices
 // 1..n0, 0 elsewhere; covers slices -kShiftPre .. n0 + 47.
 __device__ __forceinline__ void stage_shifts(uint8_t* shb, const uint32_t* __restrict__ words,
-                                             const TripletDesc& td) {
+                                             const TripletDesc& td, int tid, int nthreads) {
   const int n0 = (int)td.len[0];
   const int total = n0 + 64;
-  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+  for (int q = tid; q < total; q += nthreads) {
     const int i = q - kShiftPre;
     uint32_t v = 0;
     if (i >= 1 && i <= n0) v = residue_at(words, td.off[0], (uint32_t)(i - 1)) << 3;
@@ -196,9 +204,14 @@ __device__ __forceinline__ void stage_shifts(uint8_t* shb, const uint32_t* __res
 //             to LDS rows that the memory wave writes out (panel jobs).
 enum PanelMode { kPlain = 0, kTagged = 1, kSplitCompute = 2 };
 
+// Rows of the right out ring (a multiple of kChunk).
+constexpr int kRingR = 64;
+static_assert(kRingR % kChunk == 0 && kRingR >= kRing, "right out ring");
+
 // LDS hand-over between the two waves of a panel workgroup. Ring row
 // t mod kRing of the halo rings serves step t; out row t mod kRing holds the
-// edges the compute wave produced at step t. The counters only grow:
+// bottom edge the compute wave produced at step t, right out row (t - 7) mod
+// kRingR its right edge. The counters only grow:
 // in_ready = steps whose halo rows are staged (memory wave), out_done =
 // steps computed (compute wave), out_flushed = out rows read back by the
 // memory wave. A wave's LDS operations are performed in order, so a counter
@@ -207,11 +220,16 @@ template <int RJ, int RK>
 struct SplitLds {
   static constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
   Lds<RJ, RK> L;
-  // Out rows: bottom rows (kRing x W) followed by right rows (kRing x RR).
-  __attribute__((aligned(16))) int out[kRing * (W + RR)];
+  // Out rows: bottom rows (kRing x W) followed by right rows (kRingR x RR).
+  __attribute__((aligned(16))) int out[kRing * W + kRingR * RR];
   int in_ready, out_done, out_flushed, job;
   __device__ int* out_bot(int t) { return &out[(t & (kRing - 1)) * W]; }
-  __device__ int* out_right(int t) { return &out[kRing * W + (t & (kRing - 1)) * RR]; }
+  // The right out row of step t sits at ring row (t - 7) mod kRingR: a right
+  // neighbour's step t' needs exactly this wave's row t' + 7, so it finds it
+  // at ring row t' mod kRingR. The right rows' ring is deeper than the others
+  // so that a neighbour in the workgroup reading them in place holds this
+  // wave back only when it falls kRingR + 7 steps behind.
+  __device__ int* out_right(int t) { return &out[kRing * W + ((t - (kGK - 1)) & (kRingR - 1)) * RR]; }
 };
 
 __device__ __forceinline__ int lds_get(const int* p) {
@@ -238,7 +256,7 @@ __device__ __forceinline__ void lds_put(int* p, int v) {
 // move into the padding that consumes a padding residue scores -128, and the
 // remaining moves mirror moves inside the tensor at gap <= 0); slices outside
 // 0..n0 are excluded from the best and unfloored before slice 0.
-template <int MODE, int KIND, bool PLANE, int RJ, int RK>
+template <int MODE, int KIND, bool PLANE, int RJ, int RK, int XCH = 0>
 __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring& sc,
                            const uint32_t* __restrict__ words, const TripletDesc& td, int pj, int pk,
                            const PanelIO& io, int32_t* score_out, int* plane, int* capt,
@@ -469,14 +487,38 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
   L.sX[lane] = kSent;
 
   // Per-lane LDS sources of the three halos: ring rows for edge lanes,
-  // neighbour slots (written one step earlier) otherwise.
+  // neighbour slots (written one step earlier) otherwise. With the register
+  // exchange (XCH) every lane reads the ring rows and the inner lanes then
+  // take their neighbours' values from registers instead (below).
   const bool y0 = y == 0, x0 = x == 0;
-  const int* t_base = y0 ? &L.ringT[0][x * RK] : &L.sB[y0 ? 0 : lane - 8][0];
-  const int t_str = y0 ? W : 0;
-  const int* c_base = y0 ? &L.ringC[0][x] : &L.sX[y0 ? 0 : lane - 8];
-  const int c_str = y0 ? kGK : 0;
-  const int* l_base = x0 ? &L.ringL[0][y * RJ] : &L.sR[x0 ? 0 : lane - 1][0];
-  const int l_str = x0 ? H : 0;
+  const bool tring = XCH || y0, lring = XCH || x0;
+  const int* t_base = tring ? &L.ringT[0][x * RK] : &L.sB[y0 ? 0 : lane - 8][0];
+  const int t_str = tring ? W : 0;
+  const int* c_base = tring ? &L.ringC[0][x] : &L.sX[y0 ? 0 : lane - 8];
+  int c_str = tring ? kGK : 0;
+  const int* l_base = lring ? &L.ringL[0][y * RJ] : &L.sR[x0 ? 0 : lane - 1][0];
+  int l_str = lring ? H : 0;
+  // Register exchange: byte address of the lane above (lane - 8) for
+  // ds_bpermute; the lane to the left (lane - 1) is one DPP row shift away.
+  const int up_addr = ((lane + 64 - kGK) & 63) << 2;
+  if (SPC && io.lds_left) {
+    // Left face straight from the left neighbour's right out rows (row t of
+    // the ring holds its step t + 7): the halo of lane (y, 0) at entry
+    // 4 + y*RJ, the corner of lane (0, 0) at entry 0.
+    const int* lr = io.lds_left + kRing * W;
+    if (x0) {
+      l_base = lr + 4 + y * RJ;
+      l_str = RR;
+    }
+    if (x0 && y0) {
+      c_base = lr;
+      c_str = RR;
+    }
+  }
+  // Chunk phase of each halo source: staged rings hold two chunks; the left
+  // neighbour's right out rows, read in place, kRingR / kChunk.
+  const int l_cmask = (SPC && io.lds_left && x0) ? kRingR / kChunk - 1 : 1;
+  const int c_cmask = (SPC && io.lds_left && x0 && y0) ? kRingR / kChunk - 1 : 1;
 
   // Edge stores: bottom row (y = 7), right column (x = 7), and the corner
   // for the next panel (lane (0,7)), all into row t at step t.
@@ -498,7 +540,9 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
   // every step of prefetch distance would add a step to the lag between a
   // producer panel and its consumers.
   constexpr int kStageAt = WIDE ? kWideStageAt : 0;
-  int fin = 0, ffl = 0;  // last read in_ready / out_flushed (split compute wave)
+  // Last read in_ready / out_flushed, and the neighbours' step counters
+  // (split compute wave).
+  int fin = 0, ffl = 0, pdn = 0, cdn = 0;
   bool gave_up = false;
   auto run_chunk = [&](int c, bool cap, bool more) {
     const uint32_t cbase = (uint32_t)(c * kChunk);
@@ -506,8 +550,8 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
                    vc = vo_corner + cbase * RRB;
     const int rr = (c & 1) * kChunk;
     const int* tb = t_base + rr * t_str;
-    const int* cb = c_base + rr * c_str;
-    const int* lb = l_base + rr * l_str;
+    const int* cb = c_base + (c & c_cmask) * kChunk * c_str;
+    const int* lb = l_base + (c & l_cmask) * kChunk * l_str;
     const uint8_t* sp = shb + sh_base + c * kChunk;
     // The chunk's lookup shifts, read together: one LDS round trip per chunk
     // instead of one per step ahead of the halo reads.
@@ -518,18 +562,30 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
     for (int s = 0; s < kChunk; ++s) {
       if (!SPC && s == kStageAt && more) stage_load(c + 1);
       const int t = c * kChunk + s;
-      int fin_next = 0, ffl_next = 0;
+      int fin_next = 0, ffl_next = 0, pdn_next = 0, cdn_next = 0;
       if (SPC) {
         // Step t needs its halo rows staged (in_ready > t) and out row
         // t mod kRing read back (out_flushed > t - kRing). The counters
         // read during the previous step usually already say so; the reads
         // for the next step are issued now, behind this step's work.
-        if (!gave_up && !(fin > t && ffl > t - kRing)) {
+        // With in-workgroup neighbours also: the left neighbour has done
+        // step t + 7 (while any lane (y, 0) is on a slice <= n0), and the
+        // right neighbour has read the right out row this step overwrites
+        // (its step t - kRingR - 7).
+        const bool need_l = io.lds_left && t <= n0 + (kGJ - 1);
+        const bool need_r = io.cons_done != nullptr;
+        auto ready = [&]() {
+          return fin > t && ffl > t - kRing && (!need_l || pdn > t + (kGK - 1)) &&
+                 (!need_r || cdn > t - kRingR - (kGK - 1));
+        };
+        if (!gave_up && !ready()) {
           const uint64_t t_start = wall_clock64();
           for (;;) {
             fin = lds_get(&split->in_ready);
             ffl = lds_get(&split->out_flushed);
-            if (fin > t && ffl > t - kRing) break;
+            if (need_l) pdn = lds_get(io.prod_done);
+            if (need_r) cdn = lds_get(io.cons_done);
+            if (ready()) break;
             if (wall_clock64() - t_start > io.wait_ticks) {
               // Give up waiting for the rest of the job (the score is marked
               // invalid); the job still runs to its end.
@@ -543,6 +599,8 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         fin_next = lds_get(&split->in_ready);
         ffl_next = lds_get(&split->out_flushed);
+        if (io.lds_left) pdn_next = lds_get(io.prod_done);
+        if (io.cons_done) cdn_next = lds_get(io.cons_done);
       }
       const uint32_t sh = shv[s];
       int A[RJ], B[RK];
@@ -557,7 +615,29 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
       for (int cc = 0; cc < RK; ++cc) T[cc] = tp[cc];
 #pragma unroll
       for (int r = 0; r < RJ; ++r) Lh[r] = lp[r];
-      const int corner = cb[s * c_str];
+      int corner = cb[s * c_str];
+      if (XCH) {
+        // The upper and left neighbours finished this lane's slice one step
+        // earlier: their last rows / columns are still in their P registers
+        // (the corner is the upper lane's previous left halo). The upper row
+        // comes through ds_bpermute (lane - 8, the LDS crossbar without an
+        // LDS round trip), the left column through a DPP row shift by one
+        // lane; edge lanes keep the ring values read above.
+#pragma unroll
+        for (int cc = 0; cc < RK; ++cc) {
+          const int nb = __builtin_amdgcn_ds_bpermute(up_addr, P[RJ - 1][cc]);
+          T[cc] = y0 ? T[cc] : nb;
+        }
+        {
+          const int nb = __builtin_amdgcn_ds_bpermute(up_addr, Lp[RJ - 1]);
+          corner = y0 ? corner : nb;
+        }
+#pragma unroll
+        for (int r = 0; r < RJ; ++r) {
+          const int nb = __builtin_amdgcn_update_dpp(0, P[r][RK - 1], 0x111 /* row_shr:1 */, 0xF, 0xF, true);
+          Lh[r] = x0 ? Lh[r] : nb;
+        }
+      }
       const int i = t - y - x;  // this lane's slice
 
       if (KIND == kSemiGlobal && axis_panel) {
@@ -677,11 +757,13 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
       }
       fi += g2n;
 
+      if (!XCH) {
 #pragma unroll
-      for (int r = 0; r < RJ; ++r) L.sR[lane][r] = N[r][RK - 1];
+        for (int r = 0; r < RJ; ++r) L.sR[lane][r] = N[r][RK - 1];
 #pragma unroll
-      for (int cc = 0; cc < RK; ++cc) L.sB[lane][cc] = N[RJ - 1][cc];
-      L.sX[lane] = Lh[RJ - 1];
+        for (int cc = 0; cc < RK; ++cc) L.sB[lane][cc] = N[RJ - 1][cc];
+        L.sX[lane] = Lh[RJ - 1];
+      }
 
       // Edge stores (the hardware drops lanes whose offset is kOob).
       if (SPC) {
@@ -700,6 +782,8 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
         if (lane == 0) lds_put(&split->out_done, t + 1);
         fin = fin_next;
         ffl = ffl_next;
+        pdn = pdn_next;
+        cdn = cdn_next;
       } else if (WIDE) {
         const int g = io.gen;
 #pragma unroll
@@ -833,7 +917,9 @@ __device__ __forceinline__ void finish_panel(const SweepArgs& a, uint32_t trip, 
 //    (entries of slices past n0 are never needed), copies them into the ring
 //    rows of those steps (the corner of top lane x >= 1 at step u is entry
 //    x*RK - 1 of top row u+6) and publishes in_ready; a ring row is only
-//    refilled once the compute wave has finished the step kRing earlier;
+//    refilled once the compute wave has finished the step kRing earlier (a
+//    left face that a neighbour in the workgroup hands over in LDS is not
+//    staged);
 //  * flushing: out rows the compute wave has finished are stored as
 //    (value, tag) pairs with device-coherent stores, then out_flushed is
 //    published so the compute wave may reuse those rows.
@@ -857,6 +943,8 @@ __device__ void panel_memory(SplitLds<RJ, RK>& S, const TripletDesc& td, const P
   const Rsrc r_bot = make_rsrc(io.bot ? io.bot : io.top, io.bot ? (uint64_t)frows * ts : 0);
   const Rsrc r_right = make_rsrc(io.right ? io.right : io.left, io.right ? (uint64_t)frows * RRB : 0);
   const int gen = io.gen;
+  // A left face read from a neighbour in the workgroup is not staged.
+  const bool stage_left = io.lds_left == nullptr;
   // Flat LDS views: out rows (outB then outR), and the halo rings, with a
   // per-lane sink slot for entries a batch does not publish.
   const int* outs = S.out;
@@ -881,7 +969,7 @@ __device__ void panel_memory(SplitLds<RJ, RK>& S, const TripletDesc& td, const P
 #pragma unroll
       for (int q = 0; q < QL; ++q) {
         const int f = q * 64 + lane;
-        const uint32_t off = f < LEFTN ? (uint32_t)(((u + kGK - 1) * RR + f) * 8) : kOob;
+        const uint32_t off = f < LEFTN && stage_left ? (uint32_t)(((u + kGK - 1) * RR + f) * 8) : kOob;
         lv[q] = __builtin_amdgcn_raw_buffer_load_b64(r_left, off, opaque_zero(), kCohDevice);
       }
       // Bit k of `bad` is set when step u + k lacks one of this lane's
@@ -900,7 +988,7 @@ __device__ void panel_memory(SplitLds<RJ, RK>& S, const TripletDesc& td, const P
         const int f = q * 64 + lane;
         const int rr = f / RR, e = f % RR;  // left row u + 7 + rr
         const int slice = u + rr - (e == 0 ? 0 : (e - 4) / RJ);
-        const bool stale = f < LEFTN && (e == 0 || e >= 4) && slice <= n0 && lv[q].y < gen;
+        const bool stale = stage_left && f < LEFTN && (e == 0 || e >= 4) && slice <= n0 && lv[q].y < gen;
         bad |= stale ? 1u << rr : 0u;
       }
       int k = nb;
@@ -935,7 +1023,7 @@ __device__ void panel_memory(SplitLds<RJ, RK>& S, const TripletDesc& td, const P
           const int f = q * 64 + lane;
           const int rr = f / RR, e = f % RR;
           const int st = u + rr;
-          int* dl = !(f < LEFTN && st < hi) ? sink
+          int* dl = !(stage_left && f < LEFTN && st < hi) ? sink
                     : e == 0                 ? &S.L.ringC[st & (kRing - 1)][0]
                     : e >= 4                 ? &S.L.ringL[st & (kRing - 1)][e - 4]
                                              : sink;
@@ -960,7 +1048,8 @@ __device__ void panel_memory(SplitLds<RJ, RK>& S, const TripletDesc& td, const P
         const int row = f / EPR, e = f % EPR;
         const int t = flushed + row, ro = t & (kRing - 1);
         const int er = e == W ? 0 : 4 + (e - W - 1);  // right-face entry
-        v[q] = outs[e < W ? ro * W + e : kRing * W + ro * RR + er];
+        const int rro = (t - (kGK - 1)) & (kRingR - 1);  // right out rows sit 7 steps back
+        v[q] = outs[e < W ? ro * W + e : kRing * W + rro * RR + er];
         const bool live = row < nf;
         ob[q] = live && e < W ? (uint32_t)((t * W + e) * 8) : kOob;
         orr[q] = live && e >= W ? (uint32_t)((t * RR + er) * 8) : kOob;
@@ -988,7 +1077,7 @@ __device__ void panel_memory(SplitLds<RJ, RK>& S, const TripletDesc& td, const P
 // moves faces (panel_memory). The workgroup pops jobs from the same queue
 // and in the same dependency order as k_sweep, so the same residency
 // argument holds: every producer was popped earlier by a running workgroup.
-template <int RJ, int RK, int WPE, int KIND, bool PLANE>
+template <int RJ, int RK, int WPE, int KIND, bool PLANE, int XCH>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE))) k_panel(SweepArgs a) {
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
   __shared__ SplitLds<RJ, RK> S;
@@ -1006,7 +1095,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
     const TripletDesc td = a.desc[jd.trip];
     int* plane = PLANE ? a.plane + a.plane_off[jd.trip] : nullptr;
     if (jd.trip != staged) {
-      stage_shifts(shb, a.words, td);
+      stage_shifts(shb, a.words, td, threadIdx.x, blockDim.x);
       staged = jd.trip;
     }
     if (threadIdx.x == 0) {
@@ -1035,7 +1124,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
     int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
     int best = 0;
     if (wave == 0)
-      best = sweep_panel<kSplitCompute, KIND, PLANE, RJ, RK>(S.L, shb, a.sc, a.words, td, pj, pk, io,
+      best = sweep_panel<kSplitCompute, KIND, PLANE, RJ, RK, XCH>(S.L, shb, a.sc, a.words, td, pj, pk, io,
                                                              so, plane, capt, &S);
     else
       panel_memory<RJ, RK>(S, td, io);
@@ -1051,6 +1140,128 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
   }
 }
 
+// Strip workgroups: kPairs (compute, memory) wave pairs sweep kPairs
+// horizontally adjacent panels of one panel row together, a strip job. Each
+// pair runs the two-wave panel protocol of k_panel on its panel, except that
+// the face between two neighbours of the strip never leaves LDS: the right
+// compute wave reads the left one's right out rows in place (its memory wave
+// stages only the top face), and the left one's memory wave does not write
+// that face out. Only the strip's outer faces (top and bottom of every panel,
+// left of the first, right of the last) travel through L2/HBM. Along a panel
+// row, three of every four hand-overs thus take a few LDS operations instead
+// of a store, its coherence and a polled load. The hardware spreads the
+// workgroup's waves over the compute unit's four SIMDs; every wave reads its
+// SIMD at start and the compute role goes to the first wave on each SIMD, so
+// the four compute waves sit on distinct SIMDs whenever the waves span all
+// four.
+constexpr int kPairs = kStripPanels;
+template <int RJ, int RK, int WPE, int KIND, bool PLANE, int XCH>
+__global__ void __launch_bounds__(128 * kPairs) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_panel_group(SweepArgs a) {
+  constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
+  __shared__ SplitLds<RJ, RK> SP[kPairs];
+  __shared__ int capt_all[PLANE ? kPairs * 64 * RJ * RK : 1];
+  __shared__ int simd_of[2 * kPairs];
+  __shared__ int job_slot;
+  extern __shared__ uint8_t shb[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) simd_of[wave] = (int)((__builtin_amdgcn_s_getreg((31 << 11) | 4) >> 4) & 3u);
+  __syncthreads();
+  // Roles, the same table in every wave: compute waves are the first wave
+  // found on each SIMD (then, if fewer SIMDs hold waves, the first waves
+  // left); the others are memory waves; the p-th compute wave and the p-th
+  // memory wave form pair p, which sweeps panel p of the strip.
+  int is_comp = 0, pair = 0;
+  {
+    uint32_t comp_mask = 0, seen = 0;
+    int ncomp = 0;
+    for (int w = 0; w < 2 * kPairs; ++w) {
+      const uint32_t sb = 1u << simd_of[w];
+      if (!(seen & sb) && ncomp < kPairs) {
+        seen |= sb;
+        comp_mask |= 1u << w;
+        ++ncomp;
+      }
+    }
+    for (int w = 0; w < 2 * kPairs && ncomp < kPairs; ++w)
+      if (!(comp_mask & (1u << w))) {
+        comp_mask |= 1u << w;
+        ++ncomp;
+      }
+    is_comp = (comp_mask >> wave) & 1;
+    const uint32_t same_role = is_comp ? comp_mask : ~comp_mask;
+    pair = __builtin_popcount(same_role & ((1u << wave) - 1u));
+  }
+  SplitLds<RJ, RK>& S = SP[pair];
+  int* capt = PLANE ? &capt_all[pair * 64 * RJ * RK] : capt_all;
+  const int gen = __hip_atomic_load(a.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t staged = 0xFFFFFFFFu;
+  for (;;) {
+    if (threadIdx.x == 0) job_slot = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int idx = job_slot;
+    if (idx >= (int)a.njobs) break;
+    const JobDesc jd = a.jobs[idx];
+    const TripletDesc td = a.desc[jd.trip];
+    int* plane = PLANE ? a.plane + a.plane_off[jd.trip] : nullptr;
+    if (jd.trip != staged) {
+      stage_shifts(shb, a.words, td, threadIdx.x, blockDim.x);
+      staged = jd.trip;
+    }
+    if (lane == 0 && is_comp) {
+      S.in_ready = 0;
+      S.out_done = 0;
+      S.out_flushed = 0;
+    }
+    __syncthreads();
+    const int n1 = (int)td.len[1], n2 = (int)td.len[2];
+    const int PJ = n1 / H + 1, PK = n2 / W + 1;
+    const uint64_t rows = face_rows(td.len[0]);
+    // The strip: panels jd.panel .. jd.panel + kPairs - 1 of one panel row
+    // (those past the row's last panel are idle for this job).
+    const uint32_t p = jd.panel + (uint32_t)pair;
+    const int pj = (int)(jd.panel / (uint32_t)PK), pk = (int)(jd.panel % (uint32_t)PK) + pair;
+    const bool active = pk < PK;
+    const bool has_right_in_wg = active && pair + 1 < kPairs && pk + 1 < PK;
+    const bool has_left_in_wg = active && pair > 0;
+    int best = 0;
+    int32_t* so = nullptr;
+    PanelIO io;
+    if (active) {
+      const uint64_t fb_ints = rows * W * 2;
+      const uint64_t per_panel = fb_ints + rows * RR * 2;
+      int* pool = a.pface + td.face_off;
+      int* base = pool + (uint64_t)p * per_panel;
+      io.top = pj ? pool + (uint64_t)(p - PK) * per_panel : (pk ? a.bnd_tagged[1] : a.bnd_tagged[0]);
+      io.left = pk ? pool + (uint64_t)(p - 1) * per_panel + fb_ints : a.bnd_tagged[2];
+      io.bot = pj + 1 < PJ ? base : nullptr;
+      io.right = (pk + 1 < PK && !has_right_in_wg) ? base + fb_ints : nullptr;
+      io.gen = gen;
+      io.err = a.ctl + 1;
+      io.wait_ticks = a.wait_ticks;
+      if (has_left_in_wg) {
+        io.lds_left = SP[pair - 1].out;
+        io.prod_done = &SP[pair - 1].out_done;
+      }
+      if (has_right_in_wg) io.cons_done = &SP[pair + 1].out_done;
+      so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
+      if (is_comp)
+        best = sweep_panel<kSplitCompute, KIND, PLANE, RJ, RK, XCH>(S.L, shb, a.sc, a.words, td, pj, pk, io,
+                                                               so, plane, capt, &S);
+      else
+        panel_memory<RJ, RK>(S, td, io);
+    }
+    __syncthreads();
+    // Every wave of the strip is done with the job (see k_panel).
+    if (active && is_comp) {
+      if (KIND != kGlobal)
+        finish_panel(a, jd.trip, td.out, PJ * PK, best);
+      else if (so && lane == 0)
+        publish_score(so, split_score(S.L, td, pj, pk, a.sc.gap2), io.err);
+    }
+  }
+}
+
 // The persistent scoring kernel. Waves pop jobs from a device queue in
 // the order the host wrote them (every job after the jobs it depends on):
 //  * a whole-triplet job sweeps all panels of one triplet, in place, in the
@@ -1062,7 +1273,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
 //    waves of the grid are resident.
 // MODES: bit 0 = the plan has whole-triplet jobs, bit 1 = panel jobs; a
 // kernel built for one kind only carries no registers for the other.
-template <int RJ, int RK, int WPE, int MODES, int KIND, bool PLANE>
+template <int RJ, int RK, int WPE, int MODES, int KIND, bool PLANE, int XCH>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) k_sweep(SweepArgs a) {
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
   __shared__ Lds<RJ, RK> L;
@@ -1081,7 +1292,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
     const TripletDesc td = a.desc[jd.trip];
     int* plane = PLANE ? a.plane + a.plane_off[jd.trip] : nullptr;
     if (jd.trip != staged) {
-      stage_shifts(shb, a.words, td);
+      stage_shifts(shb, a.words, td, threadIdx.x, blockDim.x);
       staged = jd.trip;
     }
     const int n0 = (int)td.len[0], n1 = (int)td.len[1], n2 = (int)td.len[2];
@@ -1104,7 +1315,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
           io.err = nullptr;
           io.wait_ticks = 0;
           int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
-          best = max(best, sweep_panel<kPlain, KIND, PLANE, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk,
+          best = max(best, sweep_panel<kPlain, KIND, PLANE, RJ, RK, XCH>(L, shb, a.sc, a.words, td, pj, pk,
                                                                     io, so, plane, capt));
         }
       }
@@ -1125,7 +1336,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
       io.err = a.ctl + 1;
       io.wait_ticks = a.wait_ticks;
       int32_t* so = (KIND == kGlobal && pj == PJ - 1 && pk == PK - 1) ? a.scores + td.out : nullptr;
-      const int best = sweep_panel<kTagged, KIND, PLANE, RJ, RK>(L, shb, a.sc, a.words, td, pj, pk, io,
+      const int best = sweep_panel<kTagged, KIND, PLANE, RJ, RK, XCH>(L, shb, a.sc, a.words, td, pj, pk, io,
                                                                 so, plane, capt);
       if (KIND != kGlobal)
         finish_panel(a, jd.trip, td.out, PJ * PK, best);
@@ -1171,18 +1382,20 @@ __global__ void k_prepare(int* ctl, int* counter, int* red, uint32_t nred) {
   }
 }
 
-// Kernel variants: tile shape (rows, columns, waves per SIMD), kind, and
-// whether the last slice is written out (traceback planes).
-#define TRIOSEQ_SHAPES(X)                                                          \
-  X(4, 4, 4, 0, false) X(4, 4, 2, 0, false) X(8, 4, 2, 0, false) X(4, 8, 2, 0, false) \
-  X(4, 4, 2, 1, false) X(4, 4, 2, 2, false) X(8, 4, 2, 1, false) X(8, 4, 2, 2, false) \
-  X(4, 4, 2, 0, true)
-#define TRIOSEQ_MODES(X, r, c, w, k, p) X(r, c, w, 1, k, p) X(r, c, w, 2, k, p) X(r, c, w, 3, k, p)
+// Kernel variants: tile shape (rows, columns, waves per SIMD), kind, whether
+// the last slice is written out (traceback planes), and the lane exchange
+// (0: LDS slot arrays, 1: ds_bpermute and DPP row shifts).
+#define TRIOSEQ_SHAPES(X)                                                                        \
+  X(4, 4, 4, 0, false, 0) X(4, 4, 2, 0, false, 0) X(8, 4, 2, 0, false, 0) X(4, 8, 2, 0, false, 0) \
+  X(4, 4, 2, 1, false, 0) X(4, 4, 2, 2, false, 0) X(8, 4, 2, 1, false, 0) X(8, 4, 2, 2, false, 0) \
+  X(4, 4, 2, 0, true, 0) X(4, 4, 2, 0, false, 1) X(8, 4, 2, 0, false, 1) X(4, 4, 2, 0, true, 1)
+#define TRIOSEQ_MODES(X, r, c, w, k, p, x) X(r, c, w, 1, k, p, x) X(r, c, w, 2, k, p, x) X(r, c, w, 3, k, p, x)
 
 }  // namespace
 
 bool shape_supported(const KernelShape& ks, int kind) {
-#define X(a, b, w, k, p) if (!p && ks.rj == a && ks.rk == b && ks.wpe == w && kind == k) return true;
+#define X(a, b, w, k, p, x) \
+  if (!p && ks.rj == a && ks.rk == b && ks.wpe == w && kind == k && ks.xch == x) return true;
   TRIOSEQ_SHAPES(X)
 #undef X
   return false;
@@ -1208,15 +1421,20 @@ hipError_t launch_sweep(const KernelShape& ks, int modes, const SweepArgs& a, in
   const size_t lds = shift_lds_bytes(a.lds_n0);
   const int kind = a.sc.kind;
   const bool plane = a.plane != nullptr;
-#define Y(r, c, w, m, k, p)                                                                     \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m && kind == k && plane == p) {       \
-    if (m == 2)                                                                                 \
-      hipLaunchKernelGGL((k_panel<r, c, w, k, p>), dim3(grid), dim3(128), lds, s, a);           \
+  const bool group = modes == 2 && ks.group == kPairs;
+#define Y(r, c, w, m, k, p, x)                                                                  \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m && kind == k && plane == p &&       \
+      ks.xch == x) {                                                                            \
+    if (m == 2 && group)                                                                        \
+      hipLaunchKernelGGL((k_panel_group<r, c, w, k, p, x>), dim3(grid), dim3(128 * kPairs), lds,\
+                         s, a);                                                                 \
+    else if (m == 2)                                                                            \
+      hipLaunchKernelGGL((k_panel<r, c, w, k, p, x>), dim3(grid), dim3(128), lds, s, a);        \
     else                                                                                        \
-      hipLaunchKernelGGL((k_sweep<r, c, w, m, k, p>), dim3(grid), dim3(64), lds, s, a);         \
+      hipLaunchKernelGGL((k_sweep<r, c, w, m, k, p, x>), dim3(grid), dim3(64), lds, s, a);      \
     return hipGetLastError();                                                                   \
   }
-#define X(r, c, w, k, p) TRIOSEQ_MODES(Y, r, c, w, k, p)
+#define X(r, c, w, k, p, x) TRIOSEQ_MODES(Y, r, c, w, k, p, x)
   TRIOSEQ_SHAPES(X)
 #undef X
 #undef Y
@@ -1225,13 +1443,18 @@ hipError_t launch_sweep(const KernelShape& ks, int modes, const SweepArgs& a, in
 
 hipError_t sweep_occupancy(const KernelShape& ks, int modes, int kind, bool plane, uint32_t lds_n0,
                            int* waves_per_cu) {
-#define Y(r, c, w, m, k, p)                                                                       \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m && kind == k && plane == p)           \
-    return m == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                 \
-                        waves_per_cu, k_panel<r, c, w, k, p>, 128, shift_lds_bytes(lds_n0))       \
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                 \
-                        waves_per_cu, k_sweep<r, c, w, m, k, p>, 64, shift_lds_bytes(lds_n0));
-#define X(r, c, w, k, p) TRIOSEQ_MODES(Y, r, c, w, k, p)
+  const bool group = modes == 2 && ks.group == kPairs;
+#define Y(r, c, w, m, k, p, x)                                                                    \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && modes == m && kind == k && plane == p &&         \
+      ks.xch == x)                                                                                \
+    return (m == 2 && group) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                      \
+                                   waves_per_cu, k_panel_group<r, c, w, k, p, x>, 128 * kPairs,   \
+                                   shift_lds_bytes(lds_n0))                                       \
+           : m == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
+                          waves_per_cu, k_panel<r, c, w, k, p, x>, 128, shift_lds_bytes(lds_n0))  \
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
+                          waves_per_cu, k_sweep<r, c, w, m, k, p, x>, 64, shift_lds_bytes(lds_n0));
+#define X(r, c, w, k, p, x) TRIOSEQ_MODES(Y, r, c, w, k, p, x)
   TRIOSEQ_SHAPES(X)
 #undef X
 #undef Y
