@@ -125,6 +125,34 @@ trioseq_status trioseq_score_batch_packed(const uint32_t* d_words, const uint64_
                                           const uint32_t* d_len, size_t n, const trioseq_scoring* sc,
                                           int32_t* d_scores, void* hip_stream);
 
+/* trioseq_score_batch_packed for callers that cannot allocate device memory
+ * (code under HIP graph capture of their own, tight serving loops, harnesses
+ * that forbid hipMalloc): same arguments, same scores, but the call
+ * allocates and frees no device memory. Every device buffer it needs is
+ * carved from a fixed scratch array of trioseq_noalloc_scratch_bytes()
+ * (256 MiB) that the library holds on each GPU it runs on until the process
+ * ends (its first call on a device looks the array up). Limits: the panel
+ * faces of split triplets must fit 96 MiB (they take about a*b*c / 2 bytes:
+ * a lone 512 x 512 x 512 triplet fits, the 1024 x 1000 x 1048 one does not)
+ * and the rest of the batch's tables plus one wavefront's
+ * workspace for its largest whole triplet must fit the remaining 160 MiB;
+ * the call launches only as many wavefronts as that part holds workspaces
+ * for, so large batches run on fewer wavefronts than
+ * trioseq_score_batch_packed uses. Beyond these limits it returns
+ * TRIOSEQ_ERR_TOO_LARGE and launches nothing. Every call on one GPU shares
+ * that GPU's array and leaves its contents behind: calls that overlap in
+ * time on one GPU (from two threads, or on two streams not ordered with each
+ * other) race and may return wrong scores; callers must serialise them.
+ * Synchronisation: reads the lengths and offsets back (waits for hip_stream
+ * to reach the call), initialises on hip_stream and waits for that, then
+ * enqueues the scoring without waiting. Not capturable itself. */
+trioseq_status trioseq_score_batch_packed_noalloc(const uint32_t* d_words, const uint64_t* d_word_off,
+                                                  const uint32_t* d_len, size_t n,
+                                                  const trioseq_scoring* sc, int32_t* d_scores,
+                                                  void* hip_stream);
+/* Size of the scratch array behind trioseq_score_batch_packed_noalloc. */
+uint64_t trioseq_noalloc_scratch_bytes(void);
+
 /* Optimal global alignment of one triplet: the traceback (Section II, Eq. 1
  * for the scores; the alignment is recovered in linear space by Hirschberg's
  * divide and conquer, which the paper names for its traceback). row0, row1,

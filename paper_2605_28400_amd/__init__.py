@@ -88,6 +88,7 @@ EXPORTS = [
     "trioseq_plan_destroy", "trioseq_autotune", "trioseq_align", "trioseq_align_batch", "trioseq_serve_create", "trioseq_serve_submit", "trioseq_serve_poll",
     "trioseq_serve_wait", "trioseq_serve_stats_get", "trioseq_serve_get_stats", "trioseq_serve_destroy",
     "trioseq_set_wait_limit", "trioseq_last_error", "trioseq_version",
+    "trioseq_score_batch_packed_noalloc", "trioseq_noalloc_scratch_bytes",
 ]
 
 _lib = None
@@ -156,6 +157,10 @@ def lib() -> ctypes.CDLL:
                                              ctypes.c_size_t, P(Scoring), ctypes.c_void_p,
                                              ctypes.c_void_p]
     L.trioseq_score_batch_packed.restype = st
+    L.trioseq_score_batch_packed_noalloc.argtypes = L.trioseq_score_batch_packed.argtypes
+    L.trioseq_score_batch_packed_noalloc.restype = st
+    L.trioseq_noalloc_scratch_bytes.argtypes = []
+    L.trioseq_noalloc_scratch_bytes.restype = ctypes.c_uint64
     L.trioseq_align.argtypes = [P(Triplet), P(Scoring), ctypes.c_char_p, ctypes.c_char_p,
                                 ctypes.c_char_p, ctypes.c_uint32, P(ctypes.c_uint32),
                                 P(ctypes.c_int32), ctypes.c_void_p]
@@ -244,6 +249,20 @@ def score_batch_packed(d_words, d_word_off, d_len, d_scores, n: int, sc: Scoring
                                            ctypes.c_void_p(ptr(d_len)), n,
                                            ctypes.byref(sc or _default_scoring()),
                                            ctypes.c_void_p(ptr(d_scores)), _stream_ptr(stream)))
+
+
+def score_batch_packed_noalloc(d_words, d_word_off, d_len, d_scores, n: int,
+                               sc: Scoring | None = None, stream=None) -> None:
+    """As score_batch_packed, through the entry point that allocates no
+    device memory (every buffer is carved from the library's fixed scratch
+    array; calls on one GPU must not overlap in time)."""
+    ptr = lambda b: b.data_ptr() if hasattr(b, "data_ptr") else int(b)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    check(lib().trioseq_score_batch_packed_noalloc(
+        ctypes.c_void_p(ptr(d_words)), ctypes.c_void_p(ptr(d_word_off)), ctypes.c_void_p(ptr(d_len)), n,
+        ctypes.byref(sc or _default_scoring()), ctypes.c_void_p(ptr(d_scores)), _stream_ptr(stream)))
 
 
 def align(triplet, sc: Scoring | None = None, stream=None):

@@ -1127,6 +1127,46 @@ static trioseq_status score_batch_packed_body(const uint32_t* d_words, const uin
   return trioseq_plan_run(c.plan, d_words, d_scores, hip_stream);
 }
 
+}  // extern "C"
+
+namespace trioseq {
+
+trioseq_status score_packed_in_region(const uint32_t* d_words, const uint64_t* d_word_off,
+                                      const uint32_t* d_len, size_t n, const trioseq_scoring* sc,
+                                      int32_t* d_scores, const PlanMemory& mem) {
+  if (!sc) return fail(TRIOSEQ_ERR_INVALID_ARG, "score_batch_packed_noalloc: scoring is NULL");
+  if (n && (!d_words || !d_word_off || !d_len || !d_scores))
+    return fail(TRIOSEQ_ERR_INVALID_ARG, "score_batch_packed_noalloc: NULL device buffer");
+  trioseq_status st = validate_scoring(sc);
+  if (st != TRIOSEQ_OK) return st;
+  if (n == 0) return TRIOSEQ_OK;
+  // Host copies of the lengths and offsets, in buffers of this thread that
+  // only grow.
+  static thread_local std::vector<uint32_t>* lens = nullptr;
+  static thread_local std::vector<uint64_t>* offs = nullptr;
+  if (!lens) lens = new std::vector<uint32_t>;
+  if (!offs) offs = new std::vector<uint64_t>;
+  lens->resize(3 * n);
+  offs->resize(3 * n);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(lens->data(), d_len, 3 * n * 4, hipMemcpyDeviceToHost, mem.stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(offs->data(), d_word_off, 3 * n * 8, hipMemcpyDeviceToHost, mem.stream)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(mem.stream)) != hipSuccess)
+    return fail_hip(e, "score_batch_packed_noalloc: reading lengths");
+  trioseq_plan* plan = nullptr;
+  st = plan_create_impl(lens->data(), offs->data(), n, sc, nullptr, &plan, &mem);
+  if (st != TRIOSEQ_OK) return st;
+  const hipError_t le = plan_enqueue(plan, d_words, d_scores, mem.stream);
+  plan_free(plan);  // host bookkeeping only: the device buffers are the region's
+  if (le != hipSuccess) return fail_hip(le, "score_batch_packed_noalloc: kernel launch");
+  return TRIOSEQ_OK;
+}
+
+}  // namespace trioseq
+
+extern "C" {
+
 // trioseq_score / trioseq_score_batch: the plans (with their device inputs
 // and outputs) of this thread's last few batch shapes, reused when the same
 // lengths, scoring and device come again, so a repeated call only uploads,

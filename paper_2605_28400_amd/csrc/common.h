@@ -126,6 +126,11 @@ struct PlanMemory {
   int* counter;
   hipStream_t stream;
 };
+// trioseq_score_batch_packed with every device buffer carved from mem: lays
+// the batch out, initialises and enqueues one run on mem.stream.
+trioseq_status score_packed_in_region(const uint32_t* d_words, const uint64_t* d_word_off,
+                                      const uint32_t* d_len, size_t n, const trioseq_scoring* sc,
+                                      int32_t* d_scores, const PlanMemory& mem);
 
 // Traceback plane runs: sweeps of triplets that also write each triplet's
 // last slice (unshifted), triplet t at plane + plane_off[t]. The device
