@@ -33,6 +33,11 @@ PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # semi-global adds maxima over the last slices only (O(n^2) cells).
 OPS_PER_CELL_OF = {"global": 7, "semi-global": 7, "local": 9}
 OPS_PER_CELL = OPS_PER_CELL_OF["global"]
+# Packed pairs (two triplets per lane, one 16-bit half each): 5 packed
+# additions and 3 packed three-input maxima serve two cell updates, so the
+# floor is 4 VALU instructions per cell against the same 39.32e12 lane-
+# instruction peak.
+OPS_PER_CELL_PACKED = 4
 
 WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served", "traceback")
 
@@ -55,13 +60,14 @@ TRAFFIC = {
 }
 
 
-def scoring_path(trips, kind: str, engine: int, tile: str) -> str:
+def scoring_path(trips, kind: str, engine: int, tile: str, packed: bool = False) -> str:
     """Which kernels a plan runs: "halves" (a lone global triplet whose longest
     sequence has at least 256 residues, automatic engine, 4x4 tiles: its two halves swept
     concurrently with the last-slice plane variant, then met), "split" (panel
-    jobs), or "batch" (several triplets)."""
+    jobs), "batch" (several triplets) or "batch-packed" (several triplets, two
+    per lane in 16-bit halves)."""
     if len(trips) != 1:
-        return "batch"
+        return "batch-packed" if packed else "batch"
     if kind == "global" and engine == -1 and tile in ("0x0", "4x4") and max(s.size for s in trips[0]) >= 256:
         return "halves"
     return "split"
@@ -403,7 +409,10 @@ def main():
         tuned = ts.autotune(lens, off, d_words, sc=sc, reps=2)
     plan = ts.Plan(lens, off, sc=sc, engine=args.engine, tile=(rj, rk), use_graph=bool(args.graph))
     info = plan.info()
-    path = scoring_path(trips, args.kind, args.engine, args.tile)
+    packed = bool(info["packed"])
+    path = scoring_path(trips, args.kind, args.engine, args.tile, packed)
+    if packed:
+        ops = OPS_PER_CELL_PACKED
     d_scores = torch.zeros(len(trips), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 
@@ -432,11 +441,12 @@ def main():
     rec = {
         "metric": "GCUPS", "value": round(gcups, 3), "unit": "GCUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int16x2" if packed else "int32",
         "data": "synthetic",
         "config": {"workload": workload.name, "triplets": len(trips), "cells": int(cells),
                    "seed": workload.seed, "scoring": "match +1, mismatch -1, gap -2",
-                   "kind": args.kind,
+                   "kind": args.kind, "packed_pairs": packed,
                    "engine": ["whole-triplet", "split", "mixed"][info["engine"]], "path": path,
                    "tile": f"{info['tile_rows']}x{info['tile_cols']}", "grid": info["grid"],
                    "hip_graph": bool(args.graph), "parallelism": "single GPU"},
@@ -446,12 +456,16 @@ def main():
                      "traffic": measured_traffic(workload.name, args.kind,
                                                  f"{info['tile_rows']}x{info['tile_cols']}", path),
                      "kernel_ms": round(ms_events, 4), "ops_per_cell": ops,
-                     # Eq. 1 counted as 7 sums and a 7-way maximum (13 two-input operations).
-                     "frac_13_ops_per_cell": round(cells * (ops + 6) / (ms_events * 1e-3) / 1e12
+                     # Eq. 1 counted as 7 sums and a 7-way maximum (13 two-input
+                     # operations), each an int32 instruction.
+                     "frac_13_ops_per_cell": round(cells * (OPS_PER_CELL_OF[args.kind] + 6)
+                                                   / (ms_events * 1e-3) / 1e12
                                                    / PEAK_INT32_TOPS, 4),
                      "kernel": ("k_panel plane variant (two halves swept concurrently, two-wave "
                                 "panel workgroups) + gather + meet; time of the whole plan run"
                                 if path == "halves" else
+                                "k_sweep_pk (persistent job queue of whole-triplet pairs, two "
+                                "triplets per lane in 16-bit halves)" if packed else
                                 ["k_sweep (persistent job queue, whole-triplet jobs)",
                                  "k_panel (persistent job queue, two-wave panel workgroups)",
                                  "k_sweep (persistent job queue, whole-triplet and panel jobs)"][info["engine"]])},
@@ -472,6 +486,9 @@ def main():
         b = tuned["best"]
         rec["config"]["autotuned"] = {"tile": f"{b['tile_rows']}x{b['tile_cols']}",
                                       "waves_per_simd": b["waves_per_simd"] or "auto",
+                                      "packed": b["packed"] == 2,
+                                      "lane_exchange": "registers" if b["lane_exchange"] == 2 else "lds",
+                                      "split_factor": b["split_factor"] or 4,
                                       "tried": tuned["tried"], "rejected": tuned["rejected"]}
     if len(trips) > 1 and args.per_triplet_sample > 0:
         rec["per_triplet_path"] = per_triplet(ts, torch, trips, args.per_triplet_sample, stream,

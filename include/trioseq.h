@@ -210,12 +210,19 @@ typedef struct trioseq_plan_options {
   int32_t half_split_min; /* automatic engine, one global triplet: scored by two
                              concurrent halves when its longest sequence has at least
                              this many residues; -1 = never; 0 = default (256) */
+  int32_t packed;         /* 1 = int32 lanes; 2 = two triplets per lane, 16 bits each
+                             (global scoring of batches of whole triplets whose
+                             substitution terms sub - 2*gap are all >= 0 and whose
+                             values fit the 16-bit range; exact, like the int32 path;
+                             a batch that does not qualify runs in int32); 0 = default
+                             (2 when the lane tile is left to the library, else 1) */
 } trioseq_plan_options;
 
 typedef struct trioseq_plan_info {
   int32_t engine;         /* 0 all whole, 1 all split, 2 mixed */
   int32_t tile_rows, tile_cols, grid, waves_per_cu;
   int32_t panels;         /* panel jobs of split triplets */
+  int32_t packed;         /* 1: two triplets per lane (16-bit halves); 0: int32 */
   uint64_t workspace_bytes;
   double cells;           /* sum of a*b*c over the batch */
 } trioseq_plan_info;

@@ -13,6 +13,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -287,6 +288,11 @@ struct trioseq_plan {
   int32_t* g_scores = nullptr;
   // Device buffers carved from a caller's region (not owned).
   bool borrowed = false;
+  // Packed pairs: sentinel faces (top, left) and the stored value of M' = 0.
+  bool packed = false;
+  uint32_t pk_base = 0;
+  int* d_pkbnd = nullptr;
+  uint64_t pk_top_words = 0;
 };
 
 static void plan_free(trioseq_plan* p) {
@@ -307,6 +313,7 @@ static void plan_free(trioseq_plan* p) {
   (void)hipFree(p->d_pface);
   (void)hipFree(p->d_bnd);
   (void)hipFree(p->d_red);
+  (void)hipFree(p->d_pkbnd);
   for (void* q : {(void*)p->d_hwords, (void*)p->d_gather, (void*)p->d_plane, (void*)p->d_plane_off,
                   (void*)p->d_sdesc, (void*)p->d_chunk_box, (void*)p->d_partial, (void*)p->d_hscores})
     (void)hipFree(q);
@@ -367,6 +374,68 @@ trioseq_status trioseq_packed_layout(const uint32_t* lens, size_t n, uint64_t* w
 
 namespace trioseq {
 
+// Packed pairs (two triplets per lane, one 16-bit half each): the batch's
+// whole triplets, sorted by their axis lengths, are paired neighbour with
+// neighbour (a lone last one with itself) and each pair is one job over the
+// common panel grid. Qualifies when the scoring is global, every
+// substitution term sub - 2*gap is >= 0, and every value a lane can hold
+// stays within [kPackedSentinel, kPackedMax]: values outside the tensor
+// start at kPackedSentinel and grow by at most maxA per residue along the
+// fill region (kSkew slices plus the padded panel box), M' = 0 is stored as
+// base above all of them, and base + maxA * (the longest path of the padded
+// box, drain included) must not pass kPackedMax.
+static bool pair_up(Layout* L, const trioseq_scoring& sc, const KernelShape& ks) {
+  const size_t n = L->desc.size();
+  if (sc.kind != kGlobal || L->modes != 1 || L->planes || n < 2) return false;
+  int mina = INT32_MAX, maxa = INT32_MIN;
+  for (int x = 0; x < 4; ++x)
+    for (int y = 0; y < 4; ++y) {
+      mina = std::min(mina, sc.sub[x][y] - 2 * sc.gap);
+      maxa = std::max(maxa, sc.sub[x][y] - 2 * sc.gap);
+    }
+  if (mina < 0 || maxa > 255 || !pk_shape_supported(ks)) return false;
+  const int H = panel_rows(ks), W = panel_cols(ks), RR = (int)right_face_row(ks);
+  std::vector<size_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+    const TripletDesc &da = L->desc[a], &db = L->desc[b];
+    return std::make_tuple(da.len[0], da.len[1], da.len[2]) < std::make_tuple(db.len[0], db.len[1], db.len[2]);
+  });
+  const size_t np = (n + 1) / 2;
+  uint64_t box_jk = 0, n0max = 0, stride = 0;
+  std::vector<uint64_t> cost(np);
+  for (size_t q = 0; q < np; ++q) {
+    const TripletDesc& a = L->desc[idx[2 * q]];
+    const TripletDesc& b = L->desc[idx[std::min(2 * q + 1, n - 1)]];
+    const uint32_t n0 = std::max(a.len[0], b.len[0]), n1 = std::max(a.len[1], b.len[1]),
+                   n2 = std::max(a.len[2], b.len[2]);
+    const uint64_t PJ = n1 / H + 1, PK = n2 / W + 1, rows = face_rows(n0);
+    box_jk = std::max(box_jk, PJ * H + PK * W);
+    n0max = std::max<uint64_t>(n0max, n0);
+    stride = std::max(stride, rows * (PK * W + RR));
+    cost[q] = PJ * PK * (uint64_t)(n0 + 1 + kSkew);
+  }
+  const uint64_t base = kPackedSentinel + 512 + (uint64_t)maxa * (kSkew + box_jk);
+  if (base + (uint64_t)maxa * (n0max + kSkew + kChunk + box_jk) > kPackedMax) return false;
+  std::vector<TripletDesc> desc(2 * np);
+  for (size_t q = 0; q < np; ++q) {
+    desc[2 * q] = L->desc[idx[2 * q]];
+    desc[2 * q + 1] = L->desc[idx[std::min(2 * q + 1, n - 1)]];
+  }
+  std::vector<size_t> order(np);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+  L->jobs.clear();
+  for (size_t q : order) L->jobs.push_back(JobDesc{(uint32_t)(2 * q), kWholeTriplet});
+  L->desc.swap(desc);
+  L->ks = ks;
+  L->packed = true;
+  L->pk_base = (uint32_t)base;
+  L->face_stride = (stride + 63) / 64 * 64;
+  L->lds_n0 = (uint32_t)n0max;
+  return true;
+}
+
 trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
                             const trioseq_scoring& sc, const trioseq_plan_options& o, int waves_hint,
                             Layout* L, bool planes) {
@@ -378,6 +447,7 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   if (o.grid < 0) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: negative grid");
   if (o.split_factor < 0) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: negative split_factor");
   if (o.half_split_min < -1) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: bad half_split_min");
+  if (o.packed < 0 || o.packed > 2) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: packed must be 0, 1 or 2");
   if (o.panel_group != 0 && o.panel_group != 1 && o.panel_group != 4)
     return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: panel_group must be 0, 1 or 4");
   static_assert(kStripPanels == 4, "panel_group option values");
@@ -387,7 +457,10 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   if (o.lane_exchange < 0 || o.lane_exchange > 2)
     return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: lane_exchange must be 0, 1 or 2");
   ks.xch = o.lane_exchange ? o.lane_exchange - 1 : kDefaultLaneExchange;
-  if (!shape_supported(ks, sc.kind))
+  // A shape only the packed kernels have is accepted when packing is asked
+  // for; the batch must then qualify for it (checked at the end).
+  const bool int32_shape = shape_supported(ks, sc.kind);
+  if (!int32_shape && !(o.packed == 2 && sc.kind == kGlobal && pk_shape_supported(ks)))
     return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: unsupported tile shape for this scoring kind");
   std::vector<uint64_t> offs;
   if (!off) {
@@ -499,6 +572,19 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
     }
   for (size_t t : idx)
     if (!split[t]) L->jobs.push_back(JobDesc{(uint32_t)t, kWholeTriplet});
+  // Packed pairs when asked for (any lane tile a packed kernel exists for),
+  // or by default when the tile is left to the library (4 x 4, two waves per
+  // SIMD); the batch keeps int32 lanes when it does not qualify (pair_up).
+  L->packed = false;
+  if (o.packed == 2 && o.lane_exchange != 2) {
+    pair_up(L, sc, KernelShape{o.tile_rows ? o.tile_rows : 4, o.tile_cols ? o.tile_cols : 4,
+                               o.waves_per_simd ? o.waves_per_simd : 2});
+  } else if (o.packed == 0 && !o.tile_rows && !o.tile_cols && !o.waves_per_simd && o.lane_exchange != 2) {
+    pair_up(L, sc, KernelShape{4, 4, 2});
+  }
+  if (!L->packed && !int32_shape)
+    return fail(TRIOSEQ_ERR_INVALID_ARG,
+                "plan: this tile shape exists for packed pairs only, and the batch does not qualify");
   return TRIOSEQ_OK;
 }
 
@@ -542,6 +628,7 @@ void apply_tuned(const uint32_t* lens, size_t n, int kind, trioseq_plan_options*
       if (!o->lane_exchange) o->lane_exchange = kv.second.lane_exchange;
       if (!o->split_factor) o->split_factor = kv.second.split_factor;
       if (!o->half_split_min) o->half_split_min = kv.second.half_split_min;
+      if (!o->packed) o->packed = kv.second.packed;
     }
 }
 
@@ -565,6 +652,7 @@ static hipError_t cached_occupancy(const Layout& L, int device, int* w) {
   const std::string key = std::to_string(device) + "/" + std::to_string(L.ks.rj) + "x" +
                           std::to_string(L.ks.rk) + "/" + std::to_string(L.ks.wpe) + "/" +
                           std::to_string(L.ks.group) + "/" + std::to_string(L.ks.xch) + "/" +
+                          std::to_string((int)L.packed) + "/" +
                           std::to_string(L.modes) + "/" + std::to_string(L.kind) + "/" +
                           std::to_string((int)L.planes) + "/" + std::to_string(shift_lds_bytes(L.lds_n0));
   {
@@ -575,7 +663,8 @@ static hipError_t cached_occupancy(const Layout& L, int device, int* w) {
         return hipSuccess;
       }
   }
-  hipError_t e = sweep_occupancy(L.ks, L.modes, L.kind, L.planes, L.lds_n0, w);
+  hipError_t e = L.packed ? sweep_pk_occupancy(L.ks, L.lds_n0, w)
+                         : sweep_occupancy(L.ks, L.modes, L.kind, L.planes, L.lds_n0, w);
   if (e == hipSuccess && L.modes == 2 && L.ks.group > 1) {
     // A strip workgroup's 2 * kStripPanels waves fill 4 SIMDs x (waves per
     // SIMD) slots of a compute unit; the runtime's figure for these
@@ -803,6 +892,17 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
     return region_fail(e, "sentinel faces");
   p->bnd = carve_boundary(L.ks, L.lds_n0, p->d_bnd);
   if ((e = launch_init_boundary(L.ks, p->bnd, is)) != hipSuccess) return hip_bail(e, "boundary init");
+  if (L.packed) {
+    p->packed = true;
+    p->pk_base = L.pk_base;
+    const uint64_t rows = face_rows(L.lds_n0);
+    p->pk_top_words = rows * panel_cols(L.ks);
+    const uint64_t words = p->pk_top_words + rows * right_face_row(L.ks);
+    if ((e = dalloc((void**)&p->d_pkbnd, words * 4)) != hipSuccess) return region_fail(e, "packed sentinel faces");
+    if ((e = launch_fill_packed_sentinel((uint32_t*)p->d_pkbnd, words, is)) != hipSuccess)
+      return hip_bail(e, "packed sentinel faces");
+    p->workspace_bytes += words * 4;
+  }
   p->workspace_bytes = pool_bytes + bnd_ints * sizeof(int) +
                        (uint64_t)p->red_pairs * 2 * sizeof(int) +
                        nd * sizeof(TripletDesc) + L.jobs.size() * sizeof(JobDesc) + 512;
@@ -989,6 +1089,8 @@ static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t
   SweepArgs a = make_sweep_args(d_words, p->d_desc, p->d_jobs, p->njobs, p->lds_n0, d_scores,
                                 p->d_counter, p->d_ctl, p->d_face, p->face_stride, p->d_pface,
                                 p->bnd, p->d_red, p->sc);
+  if (p->packed)
+    return launch_sweep_pk(p->ks, a, p->d_pkbnd, p->d_pkbnd + p->pk_top_words, p->pk_base, p->grid, s);
   return launch_sweep(p->ks, p->modes, a, p->grid, s);
 }
 
@@ -1033,6 +1135,7 @@ trioseq_status trioseq_plan_get_info(const trioseq_plan* p, trioseq_plan_info* i
   info->grid = p->grid;
   info->waves_per_cu = p->waves_per_cu;
   info->panels = p->panels;
+  info->packed = p->packed ? 1 : 0;
   info->workspace_bytes = p->workspace_bytes;
   info->cells = p->cells;
   return TRIOSEQ_OK;
@@ -1290,6 +1393,11 @@ static trioseq_status trioseq_autotune_body(const uint32_t* lens, const uint64_t
   }
   if (n > 1) {
     for (int f : {2, 8, 16}) cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 2, 0, 0, f});
+    if (sc->kind == kGlobal) {
+      const int pks[][3] = {{4, 4, 2}, {4, 4, 3}, {8, 4, 2}, {4, 8, 2}};
+      for (const auto& sh : pks)
+        cands.push_back(trioseq_plan_options{-1, sh[0], sh[1], 0, 0, sh[2], 0, 0, 0, 0, 2});
+    }
   } else {
     cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 2, 4});
     if (sc->kind == kGlobal)
@@ -1356,9 +1464,9 @@ static trioseq_status trioseq_autotune_body(const uint32_t* lens, const uint64_t
       r.best.waves_per_simd = c == 0 ? 0 : cands[c].waves_per_simd;
     }
     if (std::getenv("TRIOSEQ_TUNE_LOG"))
-      std::fprintf(stderr, "autotune: %dx%d wpe %d xch %d group %d split %d half %d: %.4f ms\n",
+      std::fprintf(stderr, "autotune: %dx%d wpe %d xch %d group %d split %d half %d packed %d: %.4f ms\n",
                    info.tile_rows, info.tile_cols, cands[c].waves_per_simd, cands[c].lane_exchange,
-                   cands[c].panel_group, cands[c].split_factor, cands[c].half_split_min, ms);
+                   cands[c].panel_group, cands[c].split_factor, cands[c].half_split_min, info.packed, ms);
   }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);

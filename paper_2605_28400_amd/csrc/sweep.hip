@@ -1346,6 +1346,365 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) 
   }
 }
 
+// ---- Packed pairs: two triplets per lane, one 16-bit half each. ----------
+//
+// Two triplets of a batch are swept together by one wavefront over a common
+// panel grid (each axis padded to the longer of the two), every register
+// holding the pair's two values of one cell, one per 16-bit half. A cell
+// takes 5 packed additions (v_pk_add_u16) and 3 packed three-input maxima
+// (v_pk_maximum3_f16), 4 instructions per cell update against 7 in int32.
+//
+// The maximum is a half-precision instruction used on integers, exactly:
+// every value a lane ever holds is an integer in [1024, 31743], whose bit
+// patterns are positive normal half-precision numbers (0x0400 .. 0x7BFF:
+// no zero, no subnormal, no infinity, no NaN), and for those the float
+// order of the bit patterns is the integer order; a maximum returns one of
+// its inputs unchanged. The additions are plain 16-bit integer additions.
+// What keeps every value in range (checked on the host per batch, otherwise
+// the batch takes the int32 kernels):
+//  * every substitution term s - 2*gap is >= 0, so no addition lowers a
+//    value and the lookups need no sign extension;
+//  * predecessors outside the tensor (the virtual faces, and the slices
+//    before 0 that skewed lanes compute while filling) start at kSentP =
+//    1024 and grow only along their own paths, by at most maxA per residue
+//    of the path (maxA = the largest term), to below base - 512;
+//  * a real cell holds base + M', with base above every such value and
+//    M' >= 0, so a move from outside the tensor never wins (this also
+//    replaces the -128 row and column tables of the int32 kernels); the one
+//    real start, M'(0,0,0) = 0, is set explicitly;
+//  * base + maxA * (the longest path in the padded box, drain included)
+//    stays at or below 31743.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef unsigned short u2v __attribute__((ext_vector_type(2)));
+constexpr uint32_t kSentP = 0x0400u;  // 1024 in both halves (see above)
+
+__device__ __forceinline__ uint32_t padd(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u2v, a) + __builtin_bit_cast(u2v, b));
+}
+__device__ __forceinline__ uint32_t pmax3(uint32_t a, uint32_t b, uint32_t c) {
+  const h2v x = __builtin_bit_cast(h2v, a), y = __builtin_bit_cast(h2v, b), z = __builtin_bit_cast(h2v, c);
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_maximum(__builtin_elementwise_maximum(x, y), z));
+}
+
+// Per-slice byte selectors of a pair, for v_perm_b32: slice i of the common
+// sweep picks byte code_a(i) of triplet a's table into the low half and byte
+// code_b(i) of b's table into the high half (codes of S0[i-1] for 1 <= i <=
+// n0 of that triplet, 0 elsewhere); covers slices -kShiftPre .. n0 + 47.
+__device__ __forceinline__ void stage_selectors(uint32_t* sel, const uint32_t* __restrict__ words,
+                                                const TripletDesc& ta, const TripletDesc& tb, int n0) {
+  const int total = n0 + 64;
+  for (int q = threadIdx.x & 63; q < total; q += 64) {
+    const int i = q - kShiftPre;
+    const uint32_t ca = (i >= 1 && i <= (int)ta.len[0]) ? residue_at(words, ta.off[0], (uint32_t)(i - 1)) : 0u;
+    const uint32_t cb = (i >= 1 && i <= (int)tb.len[0]) ? residue_at(words, tb.off[0], (uint32_t)(i - 1)) : 0u;
+    sel[q] = ca | 0x0C00u | ((cb + 4u) << 16) | 0x0C000000u;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+}
+
+// One panel of a pair (plain faces in the wave's workspace, one 32-bit word
+// per entry holding both halves). Captures each triplet's cell (n0, n1, n2)
+// when the panel holds it: triplet a's tile into L.cap, b's into capb.
+template <int RJ, int RK, bool FUSED>
+__device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, const DevScoring& sc,
+                               const uint32_t* __restrict__ words, const TripletDesc& ta,
+                               const TripletDesc& tb, int n0, int pj, int pk, const int* top, const int* left,
+                               int* bot, int* right, uint32_t base2) {
+  constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
+  const int lane = threadIdx.x & 63;
+  const int y = lane >> 3, x = lane & 7;
+  const int j0 = pj * H + y * RJ, k0 = pk * W + x * RK;
+  const uint32_t* bt = sc.byte_tab;
+  // Row and column tables of both triplets (code 0 outside a sequence).
+  uint32_t TBa[RJ], TBb[RJ], TCa[RK], TCb[RK], C2[RJ][RK];
+  uint32_t cca[RK], ccb[RK];
+#pragma unroll
+  for (int r = 0; r < RJ; ++r) {
+    const int j = j0 + r;
+    const uint32_t ba = (j >= 1 && j <= (int)ta.len[1]) ? residue_at(words, ta.off[1], (uint32_t)(j - 1)) : 0u;
+    const uint32_t bb = (j >= 1 && j <= (int)tb.len[1]) ? residue_at(words, tb.off[1], (uint32_t)(j - 1)) : 0u;
+    TBa[r] = pick4(ba, bt[0], bt[1], bt[2], bt[3]);
+    TBb[r] = pick4(bb, bt[0], bt[1], bt[2], bt[3]);
+  }
+#pragma unroll
+  for (int c = 0; c < RK; ++c) {
+    const int k = k0 + c;
+    cca[c] = (k >= 1 && k <= (int)ta.len[2]) ? residue_at(words, ta.off[2], (uint32_t)(k - 1)) : 0u;
+    ccb[c] = (k >= 1 && k <= (int)tb.len[2]) ? residue_at(words, tb.off[2], (uint32_t)(k - 1)) : 0u;
+    TCa[c] = pick4(cca[c], bt[0], bt[1], bt[2], bt[3]);
+    TCb[c] = pick4(ccb[c], bt[0], bt[1], bt[2], bt[3]);
+  }
+#pragma unroll
+  for (int r = 0; r < RJ; ++r)
+#pragma unroll
+    for (int c = 0; c < RK; ++c)
+      C2[r][c] = ((TBa[r] >> (cca[c] << 3)) & 0xFFu) | (((TBb[r] >> (ccb[c] << 3)) & 0xFFu) << 16);
+
+  uint32_t P[RJ][RK], D[RJ][RK], Lp[RJ], Tp[RK];
+#pragma unroll
+  for (int r = 0; r < RJ; ++r) {
+    Lp[r] = kSentP * 0x10001u;
+#pragma unroll
+    for (int c = 0; c < RK; ++c) P[r][c] = D[r][c] = kSentP * 0x10001u;
+  }
+#pragma unroll
+  for (int c = 0; c < RK; ++c) Tp[c] = kSentP * 0x10001u;
+
+  const int nsteps = n0 + 1 + kSkew;
+  const int nchunks = (nsteps + kChunk - 1) / kChunk;
+  // Capture: the lane holding cell (n1, n2) of a triplet in this panel keeps
+  // its tile at that triplet's slice n0.
+  const int rsa = (int)ta.len[1] - j0, csa = (int)ta.len[2] - k0;
+  const int rsb = (int)tb.len[1] - j0, csb = (int)tb.len[2] - k0;
+  const bool own_a = rsa >= 0 && rsa < RJ && csa >= 0 && csa < RK;
+  const bool own_b = rsb >= 0 && rsb < RJ && csb >= 0 && csb < RK;
+  const int n0a = (int)ta.len[0], n0b = (int)tb.len[0];
+
+  const uint32_t frows = face_rows((uint32_t)n0);
+  constexpr uint32_t ts = W * 4u, RRB = RR * 4u;
+  const Rsrc r_top = make_rsrc(top, (uint64_t)frows * ts);
+  const Rsrc r_left = make_rsrc(left, (uint64_t)frows * RRB);
+  const Rsrc r_bot = make_rsrc(bot ? bot : top, bot ? (uint64_t)frows * ts : 0);
+  const Rsrc r_right = make_rsrc(right ? right : left, right ? (uint64_t)frows * RRB : 0);
+
+  // Staging, as in sweep_panel (plain faces): value q of a chunk is entry
+  // lane + 64 q of the top, corner or left ring.
+  constexpr int QT = kChunk * W / 64, QC = kChunk * kGK / 64, QL = kChunk * H / 64;
+  constexpr int NPF = QT + QC + QL;
+  constexpr int RT = 64 / W, RL = 64 / H;
+  static_assert(64 % W == 0 && 64 % H == 0 && QC == 1, "ring widths must divide 64");
+  const int eT = lane % W;
+  const uint32_t offT = (uint32_t)((kGJ - 1 + lane / W) * (int)ts + eT * 4);
+  const int eC = lane % kGK;
+  const bool corner_from_left = eC == 0;
+  const uint32_t offC = corner_from_left ? (uint32_t)((kGK - 1 + lane / kGK) * (int)RRB)
+                                         : (uint32_t)((kGJ - 2 + lane / kGK) * (int)ts + (eC * RK - 1) * 4);
+  const int eL = lane % H;
+  const uint32_t offL = (uint32_t)((kGK - 1 + lane / H) * (int)RRB + (4 + eL) * 4);
+  int pf[NPF];
+  auto stage_load = [&](int c) {
+    const uint32_t cb0 = (uint32_t)(c * kChunk);
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      if (q < QT) {
+        pf[q] = (int)__builtin_amdgcn_raw_buffer_load_b32(r_top, offT, (cb0 + q * RT) * ts, 0);
+      } else if (q < QT + QC) {
+        const uint32_t ot = corner_from_left ? kOob : offC, ol = corner_from_left ? offC : kOob;
+        pf[q] = (int)(__builtin_amdgcn_raw_buffer_load_b32(r_top, ot, cb0 * ts, 0) |
+                      __builtin_amdgcn_raw_buffer_load_b32(r_left, ol, cb0 * RRB, 0));
+      } else {
+        pf[q] = (int)__builtin_amdgcn_raw_buffer_load_b32(r_left, offL, (cb0 + (q - QT - QC) * RL) * RRB, 0);
+      }
+    }
+  };
+  auto stage_finish = [&](int c) {
+    const int rr = (c & 1) * kChunk;
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      if (q < QT)
+        (&L.ringT[rr][0])[lane + 64 * q] = pf[q];
+      else if (q < QT + QC)
+        L.ringC[rr][lane] = pf[q];
+      else
+        (&L.ringL[rr][0])[lane + 64 * (q - QT - QC)] = pf[q];
+    }
+  };
+  stage_load(0);
+#pragma unroll
+  for (int r = 0; r < RJ; ++r) L.sR[lane][r] = (int)(kSentP * 0x10001u);
+#pragma unroll
+  for (int c = 0; c < RK; ++c) L.sB[lane][c] = (int)(kSentP * 0x10001u);
+  L.sX[lane] = (int)(kSentP * 0x10001u);
+
+  const bool y0 = y == 0, x0 = x == 0;
+  const int* t_base = y0 ? &L.ringT[0][x * RK] : &L.sB[y0 ? 0 : lane - 8][0];
+  const int t_str = y0 ? W : 0;
+  const int* c_base = y0 ? &L.ringC[0][x] : &L.sX[y0 ? 0 : lane - 8];
+  const int c_str = y0 ? kGK : 0;
+  const int* l_base = x0 ? &L.ringL[0][y * RJ] : &L.sR[x0 ? 0 : lane - 1][0];
+  const int l_str = x0 ? H : 0;
+  const uint32_t vo_bot = (y == kGJ - 1) ? (uint32_t)(x * RK * 4) : kOob;
+  const uint32_t vo_right = (x == kGK - 1) ? (uint32_t)((4 + y * RJ) * 4) : kOob;
+  const uint32_t vo_corner = (x == kGK - 1 && y == 0) ? 0u : kOob;
+  const int sl_base = kShiftPre - y - x;
+  const bool seed_lane = pj == 0 && pk == 0 && lane == 0;
+
+  for (int c = 0; c < nchunks; ++c) {
+    stage_finish(c);
+    const bool more = c + 1 < nchunks;
+    const int cb0 = c * kChunk;
+    const bool cap_chunk = (n0a >= cb0 - kSkew && n0a <= cb0 + kChunk - 1) ||
+                           (n0b >= cb0 - kSkew && n0b <= cb0 + kChunk - 1);
+    const uint32_t vb = vo_bot + (uint32_t)cb0 * ts, vr = vo_right + (uint32_t)cb0 * RRB,
+                   vc = vo_corner + (uint32_t)cb0 * RRB;
+    const int rr = (c & 1) * kChunk;
+    const int* tb = t_base + rr * t_str;
+    const int* cbp = c_base + rr * c_str;
+    const int* lb = l_base + rr * l_str;
+    const uint32_t* sp = sel + sl_base + cb0;
+    uint32_t selv[kChunk];
+#pragma unroll
+    for (int s = 0; s < kChunk; ++s) selv[s] = sp[s];
+#pragma unroll
+    for (int s = 0; s < kChunk; ++s) {
+      if (s == 0 && more) stage_load(c + 1);
+      const int t = cb0 + s;
+      const uint32_t sv = selv[s];
+      uint32_t A[RJ], B[RK];
+#pragma unroll
+      for (int r = 0; r < RJ; ++r) A[r] = __builtin_amdgcn_perm(TBb[r], TBa[r], sv);
+#pragma unroll
+      for (int cc = 0; cc < RK; ++cc) B[cc] = __builtin_amdgcn_perm(TCb[cc], TCa[cc], sv);
+      uint32_t T[RK], Lh[RJ];
+#pragma unroll
+      for (int cc = 0; cc < RK; ++cc) T[cc] = (uint32_t)tb[s * t_str + cc];
+#pragma unroll
+      for (int r = 0; r < RJ; ++r) Lh[r] = (uint32_t)lb[s * l_str + r];
+      const uint32_t corner = (uint32_t)cbp[s * c_str];
+      // Terms of the previous slice first (formed while the halo reads are
+      // in flight): Q = best of the single move along S0 and its two double
+      // moves, X7 the triple move. The fused form computes them cell by cell
+      // instead (no registers held for them across the tile).
+      uint32_t Q[RJ][RK], X7[RJ][RK], N[RJ][RK];
+      auto prev_terms = [&](int r, int cc) {
+        const uint32_t up_prev = r ? P[r - 1][cc] : Tp[cc];
+        const uint32_t left_prev = cc ? P[r][cc - 1] : Lp[r];
+        Q[r][cc] = pmax3(P[r][cc], padd(up_prev, A[r]), padd(left_prev, B[cc]));
+        X7[r][cc] = padd(D[r][cc], padd(A[r], B[cc]));
+      };
+      if (!FUSED) {
+#pragma unroll
+        for (int r = 0; r < RJ; ++r)
+#pragma unroll
+          for (int cc = 0; cc < RK; ++cc) prev_terms(r, cc);
+      }
+#pragma unroll
+      for (int r = 0; r < RJ; ++r)
+#pragma unroll
+        for (int cc = 0; cc < RK; ++cc) {
+          if (FUSED) prev_terms(r, cc);
+          const uint32_t up_cur = r ? N[r - 1][cc] : T[cc];
+          const uint32_t left_cur = cc ? N[r][cc - 1] : Lh[r];
+          const uint32_t diag_cur = r ? (cc ? N[r - 1][cc - 1] : Lh[r - 1]) : (cc ? T[cc - 1] : corner);
+          const uint32_t x6 = padd(diag_cur, C2[r][cc]);
+          N[r][cc] = pmax3(pmax3(Q[r][cc], X7[r][cc], x6), up_cur, left_cur);
+          // M'(0,0,0) = 0: the one real start, cell (0,0) of lane 0 of the
+          // first panel at step 0, set before any other cell reads it.
+          if (r == 0 && cc == 0) N[0][0] = (t == 0 && seed_lane) ? base2 : N[0][0];
+          D[r][cc] = x6;
+        }
+
+#pragma unroll
+      for (int r = 0; r < RJ; ++r) L.sR[lane][r] = (int)N[r][RK - 1];
+#pragma unroll
+      for (int cc = 0; cc < RK; ++cc) L.sB[lane][cc] = (int)N[RJ - 1][cc];
+      L.sX[lane] = (int)Lh[RJ - 1];
+#pragma unroll
+      for (int cc = 0; cc < RK; cc += 4)
+        __builtin_amdgcn_raw_buffer_store_b128(
+            (v4i){(int)N[RJ - 1][cc], (int)N[RJ - 1][cc + 1], (int)N[RJ - 1][cc + 2], (int)N[RJ - 1][cc + 3]},
+            r_bot, vb + (s * ts + cc * 4), 0, 0);
+#pragma unroll
+      for (int r = 0; r < RJ; r += 4)
+        __builtin_amdgcn_raw_buffer_store_b128(
+            (v4i){(int)N[r][RK - 1], (int)N[r + 1][RK - 1], (int)N[r + 2][RK - 1], (int)N[r + 3][RK - 1]},
+            r_right, vr + (s * RRB + r * 4), 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32((int)T[RK - 1], r_right, vc + s * RRB, 0, 0);
+      if (cap_chunk) {
+        const int i = t - y - x;
+        if (own_a && i == n0a) {
+#pragma unroll
+          for (int r = 0; r < RJ; ++r)
+#pragma unroll
+            for (int cc = 0; cc < RK; ++cc) L.cap[r * RK + cc] = (int)N[r][cc];
+        }
+        if (own_b && i == n0b) {
+#pragma unroll
+          for (int r = 0; r < RJ; ++r)
+#pragma unroll
+            for (int cc = 0; cc < RK; ++cc) capb[r * RK + cc] = (int)N[r][cc];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RJ; ++r) {
+        Lp[r] = Lh[r];
+#pragma unroll
+        for (int cc = 0; cc < RK; ++cc) P[r][cc] = N[r][cc];
+      }
+#pragma unroll
+      for (int cc = 0; cc < RK; ++cc) Tp[cc] = T[cc];
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+}
+
+// Persistent kernel of a packed plan: every job is a pair of whole triplets
+// (descriptors 2p and 2p + 1; a lone last triplet is paired with itself),
+// swept by one wavefront over all panels of the common grid, row by row, in
+// the wave's own face workspace. pk_bnd: plain sentinel faces holding kSentP
+// in both halves (top, then left). base2: the value of M' = 0 in both halves.
+template <int RJ, int RK, int WPE, bool FUSED>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_sweep_pk(SweepArgs a, const int* pk_top, const int* pk_left, uint32_t base) {
+  constexpr int H = kGJ * RJ, W = kGK * RK;
+  __shared__ Lds<RJ, RK> L;
+  __shared__ int capb[RJ * RK];
+  extern __shared__ uint32_t selw[];
+  int* face = a.face + (uint64_t)blockIdx.x * a.face_stride;
+  const uint32_t base2 = base * 0x10001u;
+  for (;;) {
+    if (threadIdx.x == 0) L.wsync = atomicAdd(a.counter, 1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    const int idx = __builtin_amdgcn_readfirstlane(L.wsync);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    if (idx >= (int)a.njobs) break;
+    const JobDesc jd = a.jobs[idx];
+    const TripletDesc ta = a.desc[jd.trip], tb = a.desc[jd.trip + 1];
+    const int n0 = (int)max(ta.len[0], tb.len[0]);
+    const int n1 = (int)max(ta.len[1], tb.len[1]), n2 = (int)max(ta.len[2], tb.len[2]);
+    stage_selectors(selw, a.words, ta, tb, n0);
+    const int PJ = n1 / H + 1, PK = n2 / W + 1;
+    const uint64_t rows = face_rows((uint32_t)n0);
+    int* fb = face;
+    int* fr = face + rows * (uint64_t)(PK * W);
+    const int pja = (int)ta.len[1] / H, pka = (int)ta.len[2] / W;
+    const int pjb = (int)tb.len[1] / H, pkb = (int)tb.len[2] / W;
+    for (int pj = 0; pj < PJ; ++pj) {
+      for (int pk = 0; pk < PK; ++pk) {
+        int* col = fb + (uint64_t)pk * rows * W;
+        sweep_panel_pk<RJ, RK, FUSED>(L, capb, selw, a.sc, a.words, ta, tb, n0, pj, pk, pj ? col : pk_top,
+                               pk ? fr : pk_left, pj + 1 < PJ ? col : nullptr, pk + 1 < PK ? fr : nullptr,
+                               base2);
+        // Scores of the triplets whose last cell this panel held (the owner
+        // lane's tile is in LDS; lane 0 reads the cell and stores the score).
+        if ((threadIdx.x & 63) == 0) {
+          if (pj == pja && pk == pka) {
+            const int r = (int)ta.len[1] - pja * H, cc = (int)ta.len[2] - pka * W;
+            const int v = L.cap[(r % RJ) * RK + (cc % RK)] & 0xFFFF;
+            __hip_atomic_store(a.scores + ta.out,
+                               v - (int)base + a.sc.gap2 * (int)(ta.len[0] + ta.len[1] + ta.len[2]),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          }
+          if (pj == pjb && pk == pkb) {
+            const int r = (int)tb.len[1] - pjb * H, cc = (int)tb.len[2] - pkb * W;
+            const int v = (int)((uint32_t)capb[(r % RJ) * RK + (cc % RK)] >> 16);
+            __hip_atomic_store(a.scores + tb.out,
+                               v - (int)base + a.sc.gap2 * (int)(tb.len[0] + tb.len[1] + tb.len[2]),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      }
+    }
+  }
+}
+
+// Plain sentinel faces of the packed kernels: kSentP in both halves.
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 // Sentinel faces for panels on the tensor edge, in the plain layout (one
 // int per entry) and the tagged layout (value, kTagAlways). Every value is
 // kSent except the seeded top faces' entry for k = 0 at slice 0, which is 0
@@ -1392,6 +1751,47 @@ __global__ void k_prepare(int* ctl, int* counter, int* red, uint32_t nred) {
 #define TRIOSEQ_MODES(X, r, c, w, k, p, x) X(r, c, w, 1, k, p, x) X(r, c, w, 2, k, p, x) X(r, c, w, 3, k, p, x)
 
 }  // namespace
+
+// Packed kernels: lane tile and register budget; the 4 x 4 two-wave form
+// holds the previous slice's terms for the whole tile, the others form them
+// cell by cell.
+#define TRIOSEQ_PK_SHAPES(X) X(4, 4, 2, false) X(4, 4, 3, true) X(8, 4, 2, true) X(4, 8, 2, true)
+
+bool pk_shape_supported(const KernelShape& ks) {
+#define X(r, c, w, f) if (ks.rj == r && ks.rk == c && ks.wpe == w) return true;
+  TRIOSEQ_PK_SHAPES(X)
+#undef X
+  return false;
+}
+
+hipError_t launch_sweep_pk(const KernelShape& ks, const SweepArgs& a, const int* pk_top, const int* pk_left,
+                           uint32_t base, int grid, hipStream_t s) {
+  const size_t lds = (size_t)(a.lds_n0 + 64) * 4;
+#define X(r, c, w, f)                                                                              \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w) {                                                   \
+    hipLaunchKernelGGL((k_sweep_pk<r, c, w, f>), dim3(grid), dim3(64), lds, s, a, pk_top, pk_left, \
+                       base);                                                                      \
+    return hipGetLastError();                                                                      \
+  }
+  TRIOSEQ_PK_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t sweep_pk_occupancy(const KernelShape& ks, uint32_t lds_n0, int* blocks_per_cu) {
+#define X(r, c, w, f)                                                                              \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w)                                                     \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_pk<r, c, w, f>, 64, \
+                                                        (size_t)(lds_n0 + 64) * 4);
+  TRIOSEQ_PK_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_packed_sentinel(uint32_t* p, uint64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, s, p, n, kSentP * 0x10001u);
+  return hipGetLastError();
+}
 
 bool shape_supported(const KernelShape& ks, int kind) {
 #define X(a, b, w, k, p, x) \
