@@ -216,6 +216,9 @@ typedef struct trioseq_plan_options {
                              values fit the 16-bit range; exact, like the int32 path;
                              a batch that does not qualify runs in int32); 0 = default
                              (2 when the lane tile is left to the library, else 1) */
+  int32_t staging;        /* packed pairs: 1 = face rows staged through registers into
+                             LDS; 2 = loaded straight into LDS (buffer loads to LDS);
+                             0 = default */
 } trioseq_plan_options;
 
 typedef struct trioseq_plan_info {

@@ -47,7 +47,7 @@ class PlanOptions(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
                 ("panel_group", ctypes.c_int32), ("lane_exchange", ctypes.c_int32),
                 ("split_factor", ctypes.c_int32), ("half_split_min", ctypes.c_int32),
-                ("packed", ctypes.c_int32)]
+                ("packed", ctypes.c_int32), ("staging", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -361,7 +361,7 @@ class Plan:
     def __init__(self, lens, word_off=None, sc: Scoring | None = None, engine: int = -1,
                  tile=(0, 0), grid: int = 0, use_graph: bool = False, waves_per_simd: int = 0,
                  panel_group: int = 0, lane_exchange: int = 0, split_factor: int = 0,
-                 half_split_min: int = 0, packed: int = 0):
+                 half_split_min: int = 0, packed: int = 0, staging: int = 0):
         self.lens = np.ascontiguousarray(lens, dtype=np.uint32)
         self.n = self.lens.size // 3
         off_p = None
@@ -369,7 +369,7 @@ class Plan:
             self._off = np.ascontiguousarray(word_off, dtype=np.uint64)
             off_p = self._off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
         opts = PlanOptions(engine, tile[0], tile[1], grid, 1 if use_graph else 0, waves_per_simd,
-                           panel_group, lane_exchange, split_factor, half_split_min, packed)
+                           panel_group, lane_exchange, split_factor, half_split_min, packed, staging)
         self._h = ctypes.c_void_p()
         check(lib().trioseq_plan_create(self.lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                         off_p, self.n, ctypes.byref(sc or _default_scoring()),

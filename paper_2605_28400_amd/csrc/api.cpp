@@ -448,6 +448,7 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   if (o.split_factor < 0) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: negative split_factor");
   if (o.half_split_min < -1) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: bad half_split_min");
   if (o.packed < 0 || o.packed > 2) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: packed must be 0, 1 or 2");
+  if (o.staging < 0 || o.staging > 2) return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: staging must be 0, 1 or 2");
   if (o.panel_group != 0 && o.panel_group != 1 && o.panel_group != 4)
     return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: panel_group must be 0, 1 or 4");
   static_assert(kStripPanels == 4, "panel_group option values");
@@ -460,7 +461,9 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   // A shape only the packed kernels have is accepted when packing is asked
   // for; the batch must then qualify for it (checked at the end).
   const bool int32_shape = shape_supported(ks, sc.kind);
-  if (!int32_shape && !(o.packed == 2 && sc.kind == kGlobal && pk_shape_supported(ks)))
+  KernelShape pks = ks;
+  pks.dma = o.staging == 2 ? 1 : 0;
+  if (!int32_shape && !(o.packed == 2 && sc.kind == kGlobal && pk_shape_supported(pks)))
     return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: unsupported tile shape for this scoring kind");
   std::vector<uint64_t> offs;
   if (!off) {
@@ -576,10 +579,14 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   // or by default when the tile is left to the library (4 x 4, two waves per
   // SIMD); the batch keeps int32 lanes when it does not qualify (pair_up).
   L->packed = false;
-  if (o.packed == 2 && o.lane_exchange != 2) {
-    pair_up(L, sc, KernelShape{o.tile_rows ? o.tile_rows : 4, o.tile_cols ? o.tile_cols : 4,
-                               o.waves_per_simd ? o.waves_per_simd : 2});
-  } else if (o.packed == 0 && !o.tile_rows && !o.tile_cols && !o.waves_per_simd && o.lane_exchange != 2) {
+  if (o.packed == 2) {
+    KernelShape pks{o.tile_rows ? o.tile_rows : 4, o.tile_cols ? o.tile_cols : 4,
+                    o.waves_per_simd ? o.waves_per_simd : 2};
+    pks.xch = o.lane_exchange == 2 ? 1 : 0;
+    pks.dma = o.staging == 2 ? 1 : 0;
+    pair_up(L, sc, pks);
+  } else if (o.packed == 0 && !o.tile_rows && !o.tile_cols && !o.waves_per_simd && !o.lane_exchange &&
+             !o.staging) {
     pair_up(L, sc, KernelShape{4, 4, 2});
   }
   if (!L->packed && !int32_shape)
@@ -629,6 +636,7 @@ void apply_tuned(const uint32_t* lens, size_t n, int kind, trioseq_plan_options*
       if (!o->split_factor) o->split_factor = kv.second.split_factor;
       if (!o->half_split_min) o->half_split_min = kv.second.half_split_min;
       if (!o->packed) o->packed = kv.second.packed;
+      if (!o->staging) o->staging = kv.second.staging;
     }
 }
 
@@ -1394,9 +1402,12 @@ static trioseq_status trioseq_autotune_body(const uint32_t* lens, const uint64_t
   if (n > 1) {
     for (int f : {2, 8, 16}) cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 2, 0, 0, f});
     if (sc->kind == kGlobal) {
-      const int pks[][3] = {{4, 4, 2}, {4, 4, 3}, {8, 4, 2}, {4, 8, 2}};
+      // Packed shapes: tile, waves per SIMD, lane exchange, staging.
+      const int pks[][5] = {{4, 4, 2, 0, 0}, {4, 4, 3, 0, 0}, {8, 4, 2, 0, 0}, {4, 8, 2, 0, 0},
+                            {4, 4, 2, 2, 0}, {4, 4, 2, 0, 2}, {4, 4, 3, 0, 2}, {8, 4, 2, 0, 2},
+                            {4, 8, 2, 0, 2}};
       for (const auto& sh : pks)
-        cands.push_back(trioseq_plan_options{-1, sh[0], sh[1], 0, 0, sh[2], 0, 0, 0, 0, 2});
+        cands.push_back(trioseq_plan_options{-1, sh[0], sh[1], 0, 0, sh[2], 0, sh[3], 0, 0, 2, sh[4]});
     }
   } else {
     cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 2, 4});
@@ -1464,9 +1475,10 @@ static trioseq_status trioseq_autotune_body(const uint32_t* lens, const uint64_t
       r.best.waves_per_simd = c == 0 ? 0 : cands[c].waves_per_simd;
     }
     if (std::getenv("TRIOSEQ_TUNE_LOG"))
-      std::fprintf(stderr, "autotune: %dx%d wpe %d xch %d group %d split %d half %d packed %d: %.4f ms\n",
+      std::fprintf(stderr, "autotune: %dx%d wpe %d xch %d group %d split %d half %d packed %d staging %d: %.4f ms\n",
                    info.tile_rows, info.tile_cols, cands[c].waves_per_simd, cands[c].lane_exchange,
-                   cands[c].panel_group, cands[c].split_factor, cands[c].half_split_min, info.packed, ms);
+                   cands[c].panel_group, cands[c].split_factor, cands[c].half_split_min, info.packed,
+                   cands[c].staging, ms);
   }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);

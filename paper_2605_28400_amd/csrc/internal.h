@@ -120,6 +120,9 @@ struct KernelShape {
   // Exchange between the lanes of a wavefront: 0 through per-wave LDS slot
   // arrays, 1 through ds_bpermute and DPP row shifts.
   int xch = 0;
+  // Packed kernels: faces staged straight into LDS by the loads (1) or
+  // through registers (0).
+  int dma = 0;
 };
 
 // Launchers (sweep.hip).

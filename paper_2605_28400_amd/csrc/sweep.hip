@@ -1405,7 +1405,7 @@ __device__ __forceinline__ void stage_selectors(uint32_t* sel, const uint32_t* _
 // One panel of a pair (plain faces in the wave's workspace, one 32-bit word
 // per entry holding both halves). Captures each triplet's cell (n0, n1, n2)
 // when the panel holds it: triplet a's tile into L.cap, b's into capb.
-template <int RJ, int RK, bool FUSED>
+template <int RJ, int RK, bool FUSED, int XCH, bool DMA>
 __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, const DevScoring& sc,
                                const uint32_t* __restrict__ words, const TripletDesc& ta,
                                const TripletDesc& tb, int n0, int pj, int pk, const int* top, const int* left,
@@ -1481,9 +1481,30 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
                                          : (uint32_t)((kGJ - 2 + lane / kGK) * (int)ts + (eC * RK - 1) * 4);
   const int eL = lane % H;
   const uint32_t offL = (uint32_t)((kGK - 1 + lane / H) * (int)RRB + (4 + eL) * 4);
-  int pf[NPF];
+  int pf[DMA ? 1 : NPF];
   auto stage_load = [&](int c) {
     const uint32_t cb0 = (uint32_t)(c * kChunk);
+    if (DMA) {
+      // Straight into the ring half of chunk c (lane l's word of each load
+      // lands at the destination + 4 l, which is where it belongs); the
+      // corner loads go to the same slots from the top or the left face,
+      // so each lane takes only one of them.
+      const int rr = (c & 1) * kChunk;
+      typedef __attribute__((address_space(3))) void* LdsPtr;
+#pragma unroll
+      for (int q = 0; q < QT; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_top, (LdsPtr)(&L.ringT[rr][0] + 64 * q), 4, offT,
+                                                 (cb0 + q * RT) * ts, 0, 0);
+      if (corner_from_left)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_left, (LdsPtr)&L.ringC[rr][0], 4, offC, cb0 * RRB, 0, 0);
+      else
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_top, (LdsPtr)&L.ringC[rr][0], 4, offC, cb0 * ts, 0, 0);
+#pragma unroll
+      for (int q = 0; q < QL; ++q)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_left, (LdsPtr)(&L.ringL[rr][0] + 64 * q), 4, offL,
+                                                 (cb0 + q * RL) * RRB, 0, 0);
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
       if (q < QT) {
@@ -1498,6 +1519,12 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
     }
   };
   auto stage_finish = [&](int c) {
+    if (DMA) {
+      // The loads of chunk c were issued a chunk earlier: wait for them
+      // (vmcnt counts them with the stores issued since, so wait for all).
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      return;
+    }
     const int rr = (c & 1) * kChunk;
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
@@ -1517,12 +1544,14 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
   L.sX[lane] = (int)(kSentP * 0x10001u);
 
   const bool y0 = y == 0, x0 = x == 0;
-  const int* t_base = y0 ? &L.ringT[0][x * RK] : &L.sB[y0 ? 0 : lane - 8][0];
-  const int t_str = y0 ? W : 0;
-  const int* c_base = y0 ? &L.ringC[0][x] : &L.sX[y0 ? 0 : lane - 8];
-  const int c_str = y0 ? kGK : 0;
-  const int* l_base = x0 ? &L.ringL[0][y * RJ] : &L.sR[x0 ? 0 : lane - 1][0];
-  const int l_str = x0 ? H : 0;
+  const bool tring = XCH || y0, lring = XCH || x0;
+  const int* t_base = tring ? &L.ringT[0][x * RK] : &L.sB[y0 ? 0 : lane - 8][0];
+  const int t_str = tring ? W : 0;
+  const int* c_base = tring ? &L.ringC[0][x] : &L.sX[y0 ? 0 : lane - 8];
+  const int c_str = tring ? kGK : 0;
+  const int* l_base = lring ? &L.ringL[0][y * RJ] : &L.sR[x0 ? 0 : lane - 1][0];
+  const int l_str = lring ? H : 0;
+  const int up_addr = ((lane + 64 - kGK) & 63) << 2;
   const uint32_t vo_bot = (y == kGJ - 1) ? (uint32_t)(x * RK * 4) : kOob;
   const uint32_t vo_right = (x == kGK - 1) ? (uint32_t)((4 + y * RJ) * 4) : kOob;
   const uint32_t vo_corner = (x == kGK - 1 && y == 0) ? 0u : kOob;
@@ -1560,7 +1589,26 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
       for (int cc = 0; cc < RK; ++cc) T[cc] = (uint32_t)tb[s * t_str + cc];
 #pragma unroll
       for (int r = 0; r < RJ; ++r) Lh[r] = (uint32_t)lb[s * l_str + r];
-      const uint32_t corner = (uint32_t)cbp[s * c_str];
+      uint32_t corner = (uint32_t)cbp[s * c_str];
+      if (XCH) {
+        // As in sweep_panel: inner lanes take their upper neighbour's row
+        // and corner through ds_bpermute and their left neighbour's column
+        // through a DPP row shift, from its previous-step registers.
+#pragma unroll
+        for (int cc = 0; cc < RK; ++cc) {
+          const uint32_t nb = (uint32_t)__builtin_amdgcn_ds_bpermute(up_addr, (int)P[RJ - 1][cc]);
+          T[cc] = y0 ? T[cc] : nb;
+        }
+        {
+          const uint32_t nb = (uint32_t)__builtin_amdgcn_ds_bpermute(up_addr, (int)Lp[RJ - 1]);
+          corner = y0 ? corner : nb;
+        }
+#pragma unroll
+        for (int r = 0; r < RJ; ++r) {
+          const uint32_t nb = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)P[r][RK - 1], 0x111, 0xF, 0xF, true);
+          Lh[r] = x0 ? Lh[r] : nb;
+        }
+      }
       // Terms of the previous slice first (formed while the halo reads are
       // in flight): Q = best of the single move along S0 and its two double
       // moves, X7 the triple move. The fused form computes them cell by cell
@@ -1594,11 +1642,13 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
           D[r][cc] = x6;
         }
 
+      if (!XCH) {
 #pragma unroll
-      for (int r = 0; r < RJ; ++r) L.sR[lane][r] = (int)N[r][RK - 1];
+        for (int r = 0; r < RJ; ++r) L.sR[lane][r] = (int)N[r][RK - 1];
 #pragma unroll
-      for (int cc = 0; cc < RK; ++cc) L.sB[lane][cc] = (int)N[RJ - 1][cc];
-      L.sX[lane] = (int)Lh[RJ - 1];
+        for (int cc = 0; cc < RK; ++cc) L.sB[lane][cc] = (int)N[RJ - 1][cc];
+        L.sX[lane] = (int)Lh[RJ - 1];
+      }
 #pragma unroll
       for (int cc = 0; cc < RK; cc += 4)
         __builtin_amdgcn_raw_buffer_store_b128(
@@ -1643,7 +1693,7 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
 // swept by one wavefront over all panels of the common grid, row by row, in
 // the wave's own face workspace. pk_bnd: plain sentinel faces holding kSentP
 // in both halves (top, then left). base2: the value of M' = 0 in both halves.
-template <int RJ, int RK, int WPE, bool FUSED>
+template <int RJ, int RK, int WPE, bool FUSED, int XCH, bool DMA>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_sweep_pk(SweepArgs a, const int* pk_top, const int* pk_left, uint32_t base) {
   constexpr int H = kGJ * RJ, W = kGK * RK;
@@ -1672,7 +1722,7 @@ k_sweep_pk(SweepArgs a, const int* pk_top, const int* pk_left, uint32_t base) {
     for (int pj = 0; pj < PJ; ++pj) {
       for (int pk = 0; pk < PK; ++pk) {
         int* col = fb + (uint64_t)pk * rows * W;
-        sweep_panel_pk<RJ, RK, FUSED>(L, capb, selw, a.sc, a.words, ta, tb, n0, pj, pk, pj ? col : pk_top,
+        sweep_panel_pk<RJ, RK, FUSED, XCH, DMA>(L, capb, selw, a.sc, a.words, ta, tb, n0, pj, pk, pj ? col : pk_top,
                                pk ? fr : pk_left, pj + 1 < PJ ? col : nullptr, pk + 1 < PK ? fr : nullptr,
                                base2);
         // Scores of the triplets whose last cell this panel held (the owner
@@ -1755,10 +1805,15 @@ __global__ void k_prepare(int* ctl, int* counter, int* red, uint32_t nred) {
 // Packed kernels: lane tile and register budget; the 4 x 4 two-wave form
 // holds the previous slice's terms for the whole tile, the others form them
 // cell by cell.
-#define TRIOSEQ_PK_SHAPES(X) X(4, 4, 2, false) X(4, 4, 3, true) X(8, 4, 2, true) X(4, 8, 2, true)
+// (rows, columns, waves per SIMD, fused, lane exchange, LDS-direct staging)
+#define TRIOSEQ_PK_SHAPES(X)                                                                      \
+  X(4, 4, 2, false, 0, false) X(4, 4, 3, true, 0, false) X(8, 4, 2, true, 0, false)               \
+  X(4, 8, 2, true, 0, false) X(4, 4, 2, false, 1, false) X(4, 4, 2, false, 0, true)               \
+  X(4, 4, 3, true, 0, true) X(8, 4, 2, true, 0, true) X(4, 8, 2, true, 0, true)
 
 bool pk_shape_supported(const KernelShape& ks) {
-#define X(r, c, w, f) if (ks.rj == r && ks.rk == c && ks.wpe == w) return true;
+#define X(r, c, w, f, x, d) \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && ks.xch == x && ks.dma == d) return true;
   TRIOSEQ_PK_SHAPES(X)
 #undef X
   return false;
@@ -1767,10 +1822,10 @@ bool pk_shape_supported(const KernelShape& ks) {
 hipError_t launch_sweep_pk(const KernelShape& ks, const SweepArgs& a, const int* pk_top, const int* pk_left,
                            uint32_t base, int grid, hipStream_t s) {
   const size_t lds = (size_t)(a.lds_n0 + 64) * 4;
-#define X(r, c, w, f)                                                                              \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w) {                                                   \
-    hipLaunchKernelGGL((k_sweep_pk<r, c, w, f>), dim3(grid), dim3(64), lds, s, a, pk_top, pk_left, \
-                       base);                                                                      \
+#define X(r, c, w, f, x, d)                                                                        \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && ks.xch == x && ks.dma == d) {                     \
+    hipLaunchKernelGGL((k_sweep_pk<r, c, w, f, x, d>), dim3(grid), dim3(64), lds, s, a, pk_top,    \
+                       pk_left, base);                                                             \
     return hipGetLastError();                                                                      \
   }
   TRIOSEQ_PK_SHAPES(X)
@@ -1779,10 +1834,10 @@ hipError_t launch_sweep_pk(const KernelShape& ks, const SweepArgs& a, const int*
 }
 
 hipError_t sweep_pk_occupancy(const KernelShape& ks, uint32_t lds_n0, int* blocks_per_cu) {
-#define X(r, c, w, f)                                                                              \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w)                                                     \
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_pk<r, c, w, f>, 64, \
-                                                        (size_t)(lds_n0 + 64) * 4);
+#define X(r, c, w, f, x, d)                                                                        \
+  if (ks.rj == r && ks.rk == c && ks.wpe == w && ks.xch == x && ks.dma == d)                       \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                           \
+        blocks_per_cu, k_sweep_pk<r, c, w, f, x, d>, 64, (size_t)(lds_n0 + 64) * 4);
   TRIOSEQ_PK_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
