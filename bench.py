@@ -48,9 +48,11 @@ WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served", "tr
 # Keyed by (workload, kind, lane tile, path): the autotuner may pick another
 # tile, and a lone global triplet under automatic options is scored by halves.
 TRAFFIC = {
+    ("batch_8192_len100-400", "global", "4x4", "batch-packed"): (4.9159e10, "249ee33828e878c3"),
+    ("single_1024x1000x1048", "global", "4x4", "halves"): (1.5490e9, "249ee33828e878c3"),
+    ("single_4096x4000x4150", "global", "4x4", "halves"): (7.7832e10, "249ee33828e878c3"),
+    ("single_128x128x128", "global", "4x4", "split"): (5.2664e6, "249ee33828e878c3"),
     ("batch_8192_len100-400", "global", "8x4", "batch"): (7.2410e10, "5b986628d09c52c4"),
-    ("single_1024x1000x1048", "global", "4x4", "halves"): (1.5177e9, "5b986628d09c52c4"),
-    ("single_4096x4000x4150", "global", "4x4", "halves"): (7.7511e10, "5b986628d09c52c4"),
     ("single_1024x1000x1048", "global", "4x4", "split"): (1.5689e9, "5b986628d09c52c4"),
     ("single_4096x4000x4150", "global", "4x4", "split"): (7.9174e10, "5b986628d09c52c4"),
     ("single_1024x1000x1048", "local", "4x4", "split"): (1.6522e9, "5b986628d09c52c4"),
