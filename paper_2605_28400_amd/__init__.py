@@ -308,13 +308,43 @@ def align_batch(triplets, sc: Scoring | None = None, stream=None) -> list:
     return out
 
 
-def score_batch(triplets, sc: Scoring | None = None, stream=None) -> np.ndarray:
-    """Scores of many triplets in one persistent launch (synchronous)."""
-    keep: list = []
+_ASCII = np.frombuffer(b"ACGT", dtype=np.uint8)
+
+
+def triplet_array(triplets):
+    """The C array of trioseq_triplet for many triplets, built in bulk: every
+    sequence's ASCII goes into one buffer and the pointer and length fields
+    are written through a numpy view of the array. Returns (array, buffer);
+    the buffer must outlive every call that reads the array."""
     n = len(triplets)
     arr = (Triplet * max(n, 1))()
-    for q, t in enumerate(triplets):
-        arr[q] = _triplet(t, keep)
+    if n == 0:
+        return arr, None
+    seqs = [s for t in triplets for s in t]
+    if all(isinstance(s, np.ndarray) for s in seqs):
+        lens = np.fromiter((s.size for s in seqs), dtype=np.int64, count=3 * n)
+        codes = np.concatenate(seqs).astype(np.uint8, copy=False) if lens.sum() else np.zeros(0, np.uint8)
+        data = _ASCII[codes] if codes.size else codes
+    else:
+        parts = [_as_bytes(s) for s in seqs]
+        lens = np.fromiter((len(b) for b in parts), dtype=np.int64, count=3 * n)
+        data = np.frombuffer(b"".join(parts), dtype=np.uint8)
+    buf = np.empty(max(int(lens.sum()), 1), dtype=np.uint8)
+    buf[:data.size] = data
+    starts = np.zeros(3 * n, dtype=np.int64)
+    np.cumsum(lens[:-1], out=starts[1:])
+    view = np.frombuffer(arr, dtype=np.dtype({"names": ["seq", "len"], "formats": [("<u8", 3), ("<u4", 3)],
+                                               "offsets": [Triplet.seq.offset, Triplet.len.offset],
+                                               "itemsize": ctypes.sizeof(Triplet)}), count=n)
+    view["seq"] = (buf.ctypes.data + starts).reshape(n, 3)
+    view["len"] = lens.reshape(n, 3)
+    return arr, buf
+
+
+def score_batch(triplets, sc: Scoring | None = None, stream=None) -> np.ndarray:
+    """Scores of many triplets in one persistent launch (synchronous)."""
+    n = len(triplets)
+    arr, keep = triplet_array(triplets)
     out = np.zeros(max(n, 1), dtype=np.int32)
     check(lib().trioseq_score_batch(arr, n, ctypes.byref(sc or _default_scoring()),
                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
