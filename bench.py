@@ -36,8 +36,10 @@ OPS_PER_CELL = OPS_PER_CELL_OF["global"]
 # Packed pairs (two triplets per lane, one 16-bit half each): 5 packed
 # additions and 3 packed three-input maxima serve two cell updates, so the
 # floor is 4 VALU instructions per cell against the same 39.32e12 lane-
-# instruction peak.
-OPS_PER_CELL_PACKED = 4
+# instruction peak; local scoring adds a packed floor maximum and a packed
+# running maximum per two cells.
+OPS_PER_CELL_PACKED_OF = {"global": 4, "semi-global": 4, "local": 5}
+OPS_PER_CELL_PACKED = OPS_PER_CELL_PACKED_OF["global"]
 
 WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served", "traceback")
 
@@ -414,7 +416,7 @@ def main():
     packed = bool(info["packed"])
     path = scoring_path(trips, args.kind, args.engine, args.tile, packed)
     if packed:
-        ops = OPS_PER_CELL_PACKED
+        ops = OPS_PER_CELL_PACKED_OF[args.kind]
     d_scores = torch.zeros(len(trips), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 

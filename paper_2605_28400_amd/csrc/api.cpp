@@ -290,7 +290,7 @@ struct trioseq_plan {
   bool borrowed = false;
   // Packed pairs: sentinel faces (top, left) and the stored value of M' = 0.
   bool packed = false;
-  uint32_t pk_base = 0;
+  uint32_t pk_base = 0, pk_kc = 0;
   int* d_pkbnd = nullptr;
   uint64_t pk_top_words = 0;
 };
@@ -386,14 +386,14 @@ namespace trioseq {
 // box, drain included) must not pass kPackedMax.
 static bool pair_up(Layout* L, const trioseq_scoring& sc, const KernelShape& ks) {
   const size_t n = L->desc.size();
-  if (sc.kind != kGlobal || L->modes != 1 || L->planes || n < 2) return false;
+  if (L->modes != 1 || L->planes || n < 2) return false;
   int mina = INT32_MAX, maxa = INT32_MIN;
   for (int x = 0; x < 4; ++x)
     for (int y = 0; y < 4; ++y) {
       mina = std::min(mina, sc.sub[x][y] - 2 * sc.gap);
       maxa = std::max(maxa, sc.sub[x][y] - 2 * sc.gap);
     }
-  if (mina < 0 || maxa > 255 || !pk_shape_supported(ks)) return false;
+  if (mina < 0 || maxa > 255 || !pk_shape_supported(ks, sc.kind)) return false;
   const int H = panel_rows(ks), W = panel_cols(ks), RR = (int)right_face_row(ks);
   std::vector<size_t> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
@@ -415,8 +415,20 @@ static bool pair_up(Layout* L, const trioseq_scoring& sc, const KernelShape& ks)
     stride = std::max(stride, rows * (PK * W + RR));
     cost[q] = PJ * PK * (uint64_t)(n0 + 1 + kSkew);
   }
+  // Real values: base + M' with M' <= mx per unit of index sum (a move adds
+  // at most one term per residue it consumes; the local floor and the
+  // semi-global axes add g = -2*gap per unit), over the padded box and the
+  // drain steps. Semi-global candidates M + kc need kc above g times every
+  // index sum and must stay within 16 bits (see sweep.hip).
+  const uint64_t g = sc.kind == kGlobal ? 0 : (uint64_t)(-2 * sc.gap);  // gap <= 0 for the others
+  const uint64_t mx = sc.kind == kGlobal ? (uint64_t)maxa : std::max<uint64_t>(maxa, g);
   const uint64_t base = kPackedSentinel + 512 + (uint64_t)maxa * (kSkew + box_jk);
-  if (base + (uint64_t)maxa * (n0max + kSkew + kChunk + box_jk) > kPackedMax) return false;
+  if (base + mx * (n0max + kSkew + kChunk + box_jk) > kPackedMax) return false;
+  uint64_t kc = 0;
+  if (sc.kind == kSemiGlobal) {
+    kc = g * (n0max + box_jk) + 1;
+    if (kPackedMax - base + kc > 0xFFFF) return false;
+  }
   std::vector<TripletDesc> desc(2 * np);
   for (size_t q = 0; q < np; ++q) {
     desc[2 * q] = L->desc[idx[2 * q]];
@@ -431,6 +443,7 @@ static bool pair_up(Layout* L, const trioseq_scoring& sc, const KernelShape& ks)
   L->ks = ks;
   L->packed = true;
   L->pk_base = (uint32_t)base;
+  L->pk_kc = (uint32_t)kc;
   L->face_stride = (stride + 63) / 64 * 64;
   L->lds_n0 = (uint32_t)n0max;
   return true;
@@ -463,7 +476,7 @@ trioseq_status build_layout(const uint32_t* lens, const uint64_t* off, size_t n,
   const bool int32_shape = shape_supported(ks, sc.kind);
   KernelShape pks = ks;
   pks.dma = o.staging == 2 ? 1 : 0;
-  if (!int32_shape && !(o.packed == 2 && sc.kind == kGlobal && pk_shape_supported(pks)))
+  if (!int32_shape && !(o.packed == 2 && pk_shape_supported(pks, sc.kind)))
     return fail(TRIOSEQ_ERR_INVALID_ARG, "plan: unsupported tile shape for this scoring kind");
   std::vector<uint64_t> offs;
   if (!off) {
@@ -671,7 +684,7 @@ static hipError_t cached_occupancy(const Layout& L, int device, int* w) {
         return hipSuccess;
       }
   }
-  hipError_t e = L.packed ? sweep_pk_occupancy(L.ks, L.lds_n0, w)
+  hipError_t e = L.packed ? sweep_pk_occupancy(L.ks, L.kind, L.lds_n0, w)
                          : sweep_occupancy(L.ks, L.modes, L.kind, L.planes, L.lds_n0, w);
   if (e == hipSuccess && L.modes == 2 && L.ks.group > 1) {
     // A strip workgroup's 2 * kStripPanels waves fill 4 SIMDs x (waves per
@@ -903,6 +916,7 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
   if (L.packed) {
     p->packed = true;
     p->pk_base = L.pk_base;
+    p->pk_kc = L.pk_kc;
     const uint64_t rows = face_rows(L.lds_n0);
     p->pk_top_words = rows * panel_cols(L.ks);
     const uint64_t words = p->pk_top_words + rows * right_face_row(L.ks);
@@ -1098,7 +1112,8 @@ static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t
                                 p->d_counter, p->d_ctl, p->d_face, p->face_stride, p->d_pface,
                                 p->bnd, p->d_red, p->sc);
   if (p->packed)
-    return launch_sweep_pk(p->ks, a, p->d_pkbnd, p->d_pkbnd + p->pk_top_words, p->pk_base, p->grid, s);
+    return launch_sweep_pk(p->ks, p->sc.kind, a, p->d_pkbnd, p->d_pkbnd + p->pk_top_words, p->pk_base,
+                           p->pk_kc, p->grid, s);
   return launch_sweep(p->ks, p->modes, a, p->grid, s);
 }
 
@@ -1401,14 +1416,14 @@ static trioseq_status trioseq_autotune_body(const uint32_t* lens, const uint64_t
   }
   if (n > 1) {
     for (int f : {2, 8, 16}) cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 2, 0, 0, f});
-    if (sc->kind == kGlobal) {
-      // Packed shapes: tile, waves per SIMD, lane exchange, staging.
-      const int pks[][5] = {{4, 4, 2, 0, 0}, {4, 4, 3, 0, 0}, {8, 4, 2, 0, 0}, {4, 8, 2, 0, 0},
-                            {4, 4, 2, 2, 0}, {4, 4, 2, 0, 2}, {4, 4, 3, 0, 2}, {8, 4, 2, 0, 2},
-                            {4, 8, 2, 0, 2}};
-      for (const auto& sh : pks)
+    // Packed shapes: tile, waves per SIMD, lane exchange, staging (the
+    // other kinds have the plain forms only).
+    const int pks[][5] = {{4, 4, 2, 0, 0}, {4, 4, 3, 0, 0}, {8, 4, 2, 0, 0}, {4, 8, 2, 0, 0},
+                          {4, 4, 2, 2, 0}, {4, 4, 2, 0, 2}, {4, 4, 3, 0, 2}, {8, 4, 2, 0, 2},
+                          {4, 8, 2, 0, 2}};
+    for (const auto& sh : pks)
+      if (sc->kind == kGlobal || (sh[3] == 0 && sh[4] == 0))
         cands.push_back(trioseq_plan_options{-1, sh[0], sh[1], 0, 0, sh[2], 0, sh[3], 0, 0, 2, sh[4]});
-    }
   } else {
     cands.push_back(trioseq_plan_options{-1, 4, 4, 0, 0, 2, 4});
     if (sc->kind == kGlobal)

@@ -85,9 +85,11 @@ struct Layout {
   uint64_t face_stride = 0;  // ints of whole-triplet workspace per wave
   uint64_t pool_ints = 0;    // ints of panel faces of split triplets
   // Packed pairs: desc holds pair p as entries 2p, 2p + 1 and every job is a
-  // pair; pk_base is the stored value of M' = 0 (see sweep.hip).
+  // pair; pk_base is the stored value of M' = 0, pk_kc the offset of
+  // semi-global candidates (see sweep.hip).
   bool packed = false;
   uint32_t pk_base = 0;
+  uint32_t pk_kc = 0;
   // Per-triplet reduction pairs the run needs (semi-global and local scoring
   // of split triplets): 2 * red_pairs ints.
   uint32_t red_pairs() const { return kind != 0 && (modes & 2) ? (uint32_t)desc.size() : 0u; }

@@ -143,17 +143,18 @@ hipError_t sweep_occupancy(const KernelShape& ks, int modes, int kind, bool plan
 // SIMD, global kind.
 bool shape_supported(const KernelShape& ks, int kind);
 
-// Packed pairs (two triplets per lane, 16 bits each; global scoring of
-// batches of whole triplets). Jobs hold pair p as descriptors 2p and 2p + 1.
+// Packed pairs (two triplets per lane, 16 bits each; batches of whole
+// triplets, any kind). Jobs hold pair p as descriptors 2p and 2p + 1.
 // pk_top / pk_left: plain sentinel faces of face_rows(lds_n0) rows filled by
-// launch_fill_packed_sentinel; base: the stored value of M' = 0.
+// launch_fill_packed_sentinel; base: the stored value of M' = 0; kc: the
+// offset of semi-global candidates (M + kc, kept within [1, 0xFFFF]).
 constexpr uint32_t kPackedSentinel = 1024;   // value outside the tensor
 constexpr uint32_t kPackedMax = 0x7BFF;      // largest value a lane may hold
-hipError_t launch_sweep_pk(const KernelShape& ks, const SweepArgs& a, const int* pk_top, const int* pk_left,
-                           uint32_t base, int grid, hipStream_t s);
-hipError_t sweep_pk_occupancy(const KernelShape& ks, uint32_t lds_n0, int* blocks_per_cu);
-// Whether a packed kernel of this lane tile and register budget exists.
-bool pk_shape_supported(const KernelShape& ks);
+hipError_t launch_sweep_pk(const KernelShape& ks, int kind, const SweepArgs& a, const int* pk_top,
+                           const int* pk_left, uint32_t base, uint32_t kc, int grid, hipStream_t s);
+hipError_t sweep_pk_occupancy(const KernelShape& ks, int kind, uint32_t lds_n0, int* blocks_per_cu);
+// Whether a packed kernel of this lane tile, register budget and kind exists.
+bool pk_shape_supported(const KernelShape& ks, int kind);
 hipError_t launch_fill_packed_sentinel(uint32_t* p, uint64_t n, hipStream_t s);
 
 // Traceback (traceback.hip). A split box: the forward and reversed planes

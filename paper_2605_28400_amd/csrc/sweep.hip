@@ -1385,6 +1385,17 @@ __device__ __forceinline__ uint32_t pmax3(uint32_t a, uint32_t b, uint32_t c) {
   const h2v x = __builtin_bit_cast(h2v, a), y = __builtin_bit_cast(h2v, b), z = __builtin_bit_cast(h2v, c);
   return __builtin_bit_cast(uint32_t, __builtin_elementwise_maximum(__builtin_elementwise_maximum(x, y), z));
 }
+__device__ __forceinline__ uint32_t pmax2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t,
+                            __builtin_elementwise_maximum(__builtin_bit_cast(h2v, a), __builtin_bit_cast(h2v, b)));
+}
+// Integer forms, for differences that need not be normal half patterns.
+__device__ __forceinline__ uint32_t psub(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u2v, a) - __builtin_bit_cast(u2v, b));
+}
+__device__ __forceinline__ uint32_t umax2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u2v, a), __builtin_bit_cast(u2v, b)));
+}
 
 // Per-slice byte selectors of a pair, for v_perm_b32: slice i of the common
 // sweep picks byte code_a(i) of triplet a's table into the low half and byte
@@ -1403,42 +1414,56 @@ __device__ __forceinline__ void stage_selectors(uint32_t* sel, const uint32_t* _
 }
 
 // One panel of a pair (plain faces in the wave's workspace, one 32-bit word
-// per entry holding both halves). Captures each triplet's cell (n0, n1, n2)
-// when the panel holds it: triplet a's tile into L.cap, b's into capb.
-template <int RJ, int RK, bool FUSED, int XCH, bool DMA>
+// per entry holding both halves). Global scoring captures each triplet's
+// cell (n0, n1, n2) when the panel holds it: triplet a's tile into L.cap,
+// b's into capb. Semi-global and local scoring fold the panel's cells into
+// the lane's running best (both halves; see k_sweep_pk for its meaning).
+template <int RJ, int RK, int KIND, bool FUSED, int XCH, bool DMA>
 __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, const DevScoring& sc,
                                const uint32_t* __restrict__ words, const TripletDesc& ta,
                                const TripletDesc& tb, int n0, int pj, int pk, const int* top, const int* left,
-                               int* bot, int* right, uint32_t base2) {
+                               int* bot, int* right, uint32_t base2, uint32_t& best, uint32_t kc) {
   constexpr int H = kGJ * RJ, W = kGK * RK, RR = H + 4;
+  constexpr bool PAD = KIND != kGlobal;
   const int lane = threadIdx.x & 63;
   const int y = lane >> 3, x = lane & 7;
   const int j0 = pj * H + y * RJ, k0 = pk * W + x * RK;
+  const int n1a = (int)ta.len[1], n1b = (int)tb.len[1], n2a = (int)ta.len[2], n2b = (int)tb.len[2];
   const uint32_t* bt = sc.byte_tab;
   // Row and column tables of both triplets (code 0 outside a sequence).
+  // Semi-global and local scoring take all-zero tables, per triplet, on
+  // row 0, column 0 and past the triplet's own last row and column: a move
+  // that consumes a residue which is not there then scores no better than
+  // the gaps it replaces, so those cells never beat a cell of the triplet
+  // itself (the padding argument of the int32 kernels, with 0 for -128,
+  // as no term may be negative here).
   uint32_t TBa[RJ], TBb[RJ], TCa[RK], TCb[RK], C2[RJ][RK];
   uint32_t cca[RK], ccb[RK];
+  bool za[RK], zb[RK];
 #pragma unroll
   for (int r = 0; r < RJ; ++r) {
     const int j = j0 + r;
-    const uint32_t ba = (j >= 1 && j <= (int)ta.len[1]) ? residue_at(words, ta.off[1], (uint32_t)(j - 1)) : 0u;
-    const uint32_t bb = (j >= 1 && j <= (int)tb.len[1]) ? residue_at(words, tb.off[1], (uint32_t)(j - 1)) : 0u;
-    TBa[r] = pick4(ba, bt[0], bt[1], bt[2], bt[3]);
-    TBb[r] = pick4(bb, bt[0], bt[1], bt[2], bt[3]);
+    const uint32_t ba = (j >= 1 && j <= n1a) ? residue_at(words, ta.off[1], (uint32_t)(j - 1)) : 0u;
+    const uint32_t bb = (j >= 1 && j <= n1b) ? residue_at(words, tb.off[1], (uint32_t)(j - 1)) : 0u;
+    TBa[r] = (PAD && (j == 0 || j > n1a)) ? 0u : pick4(ba, bt[0], bt[1], bt[2], bt[3]);
+    TBb[r] = (PAD && (j == 0 || j > n1b)) ? 0u : pick4(bb, bt[0], bt[1], bt[2], bt[3]);
   }
 #pragma unroll
   for (int c = 0; c < RK; ++c) {
     const int k = k0 + c;
-    cca[c] = (k >= 1 && k <= (int)ta.len[2]) ? residue_at(words, ta.off[2], (uint32_t)(k - 1)) : 0u;
-    ccb[c] = (k >= 1 && k <= (int)tb.len[2]) ? residue_at(words, tb.off[2], (uint32_t)(k - 1)) : 0u;
-    TCa[c] = pick4(cca[c], bt[0], bt[1], bt[2], bt[3]);
-    TCb[c] = pick4(ccb[c], bt[0], bt[1], bt[2], bt[3]);
+    cca[c] = (k >= 1 && k <= n2a) ? residue_at(words, ta.off[2], (uint32_t)(k - 1)) : 0u;
+    ccb[c] = (k >= 1 && k <= n2b) ? residue_at(words, tb.off[2], (uint32_t)(k - 1)) : 0u;
+    za[c] = PAD && (k == 0 || k > n2a);
+    zb[c] = PAD && (k == 0 || k > n2b);
+    TCa[c] = za[c] ? 0u : pick4(cca[c], bt[0], bt[1], bt[2], bt[3]);
+    TCb[c] = zb[c] ? 0u : pick4(ccb[c], bt[0], bt[1], bt[2], bt[3]);
   }
 #pragma unroll
   for (int r = 0; r < RJ; ++r)
 #pragma unroll
     for (int c = 0; c < RK; ++c)
-      C2[r][c] = ((TBa[r] >> (cca[c] << 3)) & 0xFFu) | (((TBb[r] >> (ccb[c] << 3)) & 0xFFu) << 16);
+      C2[r][c] = (za[c] ? 0u : ((TBa[r] >> (cca[c] << 3)) & 0xFFu)) |
+                 ((zb[c] ? 0u : ((TBb[r] >> (ccb[c] << 3)) & 0xFFu)) << 16);
 
   uint32_t P[RJ][RK], D[RJ][RK], Lp[RJ], Tp[RK];
 #pragma unroll
@@ -1454,11 +1479,33 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
   const int nchunks = (nsteps + kChunk - 1) / kChunk;
   // Capture: the lane holding cell (n1, n2) of a triplet in this panel keeps
   // its tile at that triplet's slice n0.
-  const int rsa = (int)ta.len[1] - j0, csa = (int)ta.len[2] - k0;
-  const int rsb = (int)tb.len[1] - j0, csb = (int)tb.len[2] - k0;
+  const int rsa = n1a - j0, csa = n2a - k0;
+  const int rsb = n1b - j0, csb = n2b - k0;
   const bool own_a = rsa >= 0 && rsa < RJ && csa >= 0 && csa < RK;
   const bool own_b = rsb >= 0 && rsb < RJ && csb >= 0 && csb < RK;
   const int n0a = (int)ta.len[0], n0b = (int)tb.len[0];
+
+  // Semi-global and local scoring (g = -2*gap >= 0). fi = g*(i + j0 + k0)
+  // for the lane's slice i of the current step; a cell of anti-diagonal
+  // class d = r + c of the tile lies at index sum i + j0 + k0 + d.
+  constexpr int ND = RJ + RK - 1;
+  const int g = -sc.gap2;
+  const uint32_t g2 = (uint32_t)g * 0x10001u;
+  int fi = g * (j0 + k0 - y - x);
+  // Semi-global: the halves of the rows and columns that are a triplet's
+  // last row n1 or last column n2 (masks of both halves).
+  uint32_t RM[RJ], CM[RK], rcany = 0;
+#pragma unroll
+  for (int r = 0; r < RJ; ++r) {
+    RM[r] = (r == rsa ? 0xFFFFu : 0u) | (r == rsb ? 0xFFFF0000u : 0u);
+    rcany |= RM[r];
+  }
+#pragma unroll
+  for (int c = 0; c < RK; ++c) {
+    CM[c] = (c == csa ? 0xFFFFu : 0u) | (c == csb ? 0xFFFF0000u : 0u);
+    rcany |= CM[c];
+  }
+  const bool axis_panel = pj == 0 || pk == 0;
 
   const uint32_t frows = face_rows((uint32_t)n0);
   constexpr uint32_t ts = W * 4u, RRB = RR * 4u;
@@ -1609,16 +1656,45 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
           Lh[r] = x0 ? Lh[r] : nb;
         }
       }
+      const int i = t - y - x;  // this lane's slice
+      if (KIND == kSemiGlobal && axis_panel) {
+        // The axes hold 0 (stored base + g*index, both halves): at slice 0
+        // the virtual row above the first panel row holds base + g*k and the
+        // virtual column left of the first panel column base + g*j, and at
+        // k = 0 the virtual row holds base + g*i; the single move (+0)
+        // copies them in. Other moves from there take the zero row/column-0
+        // tables and give values the single moves already reach.
+        if (j0 == 0) {
+#pragma unroll
+          for (int cc = 0; cc < RK; ++cc) T[cc] = i == 0 ? base2 + (uint32_t)(g * (k0 + cc)) * 0x10001u : T[cc];
+          if (k0 == 0) T[0] = i >= 0 ? base2 + (uint32_t)(g * i) * 0x10001u : T[0];
+        }
+        if (k0 == 0) {
+#pragma unroll
+          for (int r = 0; r < RJ; ++r) Lh[r] = i == 0 ? base2 + (uint32_t)(g * (j0 + r)) * 0x10001u : Lh[r];
+        }
+      }
+      // Local floors per anti-diagonal class, F_d = base + fi + g*d in both
+      // halves (M >= 0); none before slice 0 (0 there, below every value).
+      uint32_t F[ND];
+      if (KIND == kLocal) {
+        asm volatile("" : "+v"(fi));  // one step's floors live at a time
+        const uint32_t f0 = i >= 0 ? base2 + (uint32_t)fi * 0x10001u : 0u;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) F[d] = f0 + (uint32_t)d * g2;
+      }
       // Terms of the previous slice first (formed while the halo reads are
       // in flight): Q = best of the single move along S0 and its two double
       // moves, X7 the triple move. The fused form computes them cell by cell
-      // instead (no registers held for them across the tile).
+      // instead (no registers held for them across the tile). Local scoring
+      // folds X7 and the floor into Q.
       uint32_t Q[RJ][RK], X7[RJ][RK], N[RJ][RK];
       auto prev_terms = [&](int r, int cc) {
         const uint32_t up_prev = r ? P[r - 1][cc] : Tp[cc];
         const uint32_t left_prev = cc ? P[r][cc - 1] : Lp[r];
         Q[r][cc] = pmax3(P[r][cc], padd(up_prev, A[r]), padd(left_prev, B[cc]));
         X7[r][cc] = padd(D[r][cc], padd(A[r], B[cc]));
+        if (KIND == kLocal) Q[r][cc] = pmax3(Q[r][cc], X7[r][cc], F[r + cc]);
       };
       if (!FUSED) {
 #pragma unroll
@@ -1635,12 +1711,57 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
           const uint32_t left_cur = cc ? N[r][cc - 1] : Lh[r];
           const uint32_t diag_cur = r ? (cc ? N[r - 1][cc - 1] : Lh[r - 1]) : (cc ? T[cc - 1] : corner);
           const uint32_t x6 = padd(diag_cur, C2[r][cc]);
-          N[r][cc] = pmax3(pmax3(Q[r][cc], X7[r][cc], x6), up_cur, left_cur);
-          // M'(0,0,0) = 0: the one real start, cell (0,0) of lane 0 of the
-          // first panel at step 0, set before any other cell reads it.
-          if (r == 0 && cc == 0) N[0][0] = (t == 0 && seed_lane) ? base2 : N[0][0];
+          if (KIND == kLocal)
+            N[r][cc] = pmax3(pmax2(Q[r][cc], x6), up_cur, left_cur);
+          else
+            N[r][cc] = pmax3(pmax3(Q[r][cc], X7[r][cc], x6), up_cur, left_cur);
+          // Global M'(0,0,0) = 0: the one real start, cell (0,0) of lane 0
+          // of the first panel at step 0, set before any other cell reads it.
+          if (KIND == kGlobal && r == 0 && cc == 0) N[0][0] = (t == 0 && seed_lane) ? base2 : N[0][0];
           D[r][cc] = x6;
         }
+
+      // Masks of the halves whose triplet has this slice (0 <= i <= its n0)
+      // and of those whose last slice it is.
+      const uint32_t vm = ((uint32_t)i <= (uint32_t)n0a ? 0xFFFFu : 0u) | ((uint32_t)i <= (uint32_t)n0b ? 0xFFFF0000u : 0u);
+      if (KIND == kLocal) {
+        // M = stored value - F_d, never negative on slices from 0 (every
+        // cell is floored); the best class maximum minus its floor.
+        uint32_t sb = 0;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          uint32_t m = 0, hold = 0;
+          int cnt = 0;
+#pragma unroll
+          for (int r = 0; r < RJ; ++r) {
+            if (d - r < 0 || d - r >= RK) continue;
+            const uint32_t v = N[r][d - r];
+            if (cnt == 0) m = v;
+            else if (cnt & 1) hold = v;
+            else m = pmax3(m, hold, v);
+            ++cnt;
+          }
+          if (!(cnt & 1)) m = pmax2(m, hold);
+          sb = umax2(sb, psub(m, F[d]));
+        }
+        best = umax2(best, sb & vm);
+      } else if (KIND == kSemiGlobal) {
+        // Cells of a triplet's last slice, row or column (on its slices 0
+        // .. n0), as M + kc = stored - base - g*(i + j + k) + kc, which the
+        // host keeps within [1, 0xFFFF]; masked cells give 0.
+        const uint32_t sm = (i == n0a ? 0xFFFFu : 0u) | (i == n0b ? 0xFFFF0000u : 0u);
+        if (((rcany | sm) & vm) != 0u) {
+          const uint32_t off0 = ((uint32_t)(kc - (base2 & 0xFFFFu) - (uint32_t)fi) & 0xFFFFu) * 0x10001u;
+          uint32_t sb = 0;
+#pragma unroll
+          for (int r = 0; r < RJ; ++r)
+#pragma unroll
+            for (int cc = 0; cc < RK; ++cc)
+              sb = umax2(sb, padd(N[r][cc], psub(off0, (uint32_t)(r + cc) * g2)) & (RM[r] | CM[cc] | sm));
+          best = umax2(best, sb & vm);
+        }
+      }
+      fi += g;
 
       if (!XCH) {
 #pragma unroll
@@ -1660,8 +1781,7 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
             (v4i){(int)N[r][RK - 1], (int)N[r + 1][RK - 1], (int)N[r + 2][RK - 1], (int)N[r + 3][RK - 1]},
             r_right, vr + (s * RRB + r * 4), 0, 0);
       __builtin_amdgcn_raw_buffer_store_b32((int)T[RK - 1], r_right, vc + s * RRB, 0, 0);
-      if (cap_chunk) {
-        const int i = t - y - x;
+      if (KIND == kGlobal && cap_chunk) {
         if (own_a && i == n0a) {
 #pragma unroll
           for (int r = 0; r < RJ; ++r)
@@ -1691,11 +1811,13 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
 // Persistent kernel of a packed plan: every job is a pair of whole triplets
 // (descriptors 2p and 2p + 1; a lone last triplet is paired with itself),
 // swept by one wavefront over all panels of the common grid, row by row, in
-// the wave's own face workspace. pk_bnd: plain sentinel faces holding kSentP
-// in both halves (top, then left). base2: the value of M' = 0 in both halves.
-template <int RJ, int RK, int WPE, bool FUSED, int XCH, bool DMA>
+// the wave's own face workspace. pk_top / pk_left: plain sentinel faces
+// holding kSentP in both halves. base: the stored value of M' = 0. Local
+// scoring keeps each lane's best M per half, semi-global its best M + kc
+// (kc > 0 keeps every candidate positive); the wave's maxima are the scores.
+template <int RJ, int RK, int WPE, int KIND, bool FUSED, int XCH, bool DMA>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
-k_sweep_pk(SweepArgs a, const int* pk_top, const int* pk_left, uint32_t base) {
+k_sweep_pk(SweepArgs a, const int* pk_top, const int* pk_left, uint32_t base, uint32_t kc) {
   constexpr int H = kGJ * RJ, W = kGK * RK;
   __shared__ Lds<RJ, RK> L;
   __shared__ int capb[RJ * RK];
@@ -1719,15 +1841,17 @@ k_sweep_pk(SweepArgs a, const int* pk_top, const int* pk_left, uint32_t base) {
     int* fr = face + rows * (uint64_t)(PK * W);
     const int pja = (int)ta.len[1] / H, pka = (int)ta.len[2] / W;
     const int pjb = (int)tb.len[1] / H, pkb = (int)tb.len[2] / W;
+    uint32_t best = 0;
     for (int pj = 0; pj < PJ; ++pj) {
       for (int pk = 0; pk < PK; ++pk) {
         int* col = fb + (uint64_t)pk * rows * W;
-        sweep_panel_pk<RJ, RK, FUSED, XCH, DMA>(L, capb, selw, a.sc, a.words, ta, tb, n0, pj, pk, pj ? col : pk_top,
-                               pk ? fr : pk_left, pj + 1 < PJ ? col : nullptr, pk + 1 < PK ? fr : nullptr,
-                               base2);
+        sweep_panel_pk<RJ, RK, KIND, FUSED, XCH, DMA>(L, capb, selw, a.sc, a.words, ta, tb, n0, pj, pk,
+                                                      pj ? col : pk_top, pk ? fr : pk_left,
+                                                      pj + 1 < PJ ? col : nullptr, pk + 1 < PK ? fr : nullptr,
+                                                      base2, best, kc);
         // Scores of the triplets whose last cell this panel held (the owner
         // lane's tile is in LDS; lane 0 reads the cell and stores the score).
-        if ((threadIdx.x & 63) == 0) {
+        if (KIND == kGlobal && (threadIdx.x & 63) == 0) {
           if (pj == pja && pk == pka) {
             const int r = (int)ta.len[1] - pja * H, cc = (int)ta.len[2] - pka * W;
             const int v = L.cap[(r % RJ) * RK + (cc % RK)] & 0xFFFF;
@@ -1744,6 +1868,18 @@ k_sweep_pk(SweepArgs a, const int* pk_top, const int* pk_left, uint32_t base) {
           }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      }
+    }
+    if (KIND != kGlobal) {
+      // The wave's best per half; lane 0 stores both scores.
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) best = umax2(best, (uint32_t)__shfl_xor((int)best, o));
+      if ((threadIdx.x & 63) == 0) {
+        const int off = KIND == kSemiGlobal ? (int)kc : 0;
+        __hip_atomic_store(a.scores + ta.out, (int)(best & 0xFFFFu) - off, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(a.scores + tb.out, (int)(best >> 16) - off, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
       }
     }
   }
@@ -1805,27 +1941,33 @@ __global__ void k_prepare(int* ctl, int* counter, int* red, uint32_t nred) {
 // Packed kernels: lane tile and register budget; the 4 x 4 two-wave form
 // holds the previous slice's terms for the whole tile, the others form them
 // cell by cell.
-// (rows, columns, waves per SIMD, fused, lane exchange, LDS-direct staging)
+// (rows, columns, waves per SIMD, kind, fused, lane exchange, LDS-direct
+// staging); semi-global and local scoring exist in the four plain forms.
+#define TRIOSEQ_PK_PLAIN(X, k)                                                                    \
+  X(4, 4, 2, k, false, 0, false) X(4, 4, 3, k, true, 0, false) X(8, 4, 2, k, true, 0, false)      \
+  X(4, 8, 2, k, true, 0, false)
 #define TRIOSEQ_PK_SHAPES(X)                                                                      \
-  X(4, 4, 2, false, 0, false) X(4, 4, 3, true, 0, false) X(8, 4, 2, true, 0, false)               \
-  X(4, 8, 2, true, 0, false) X(4, 4, 2, false, 1, false) X(4, 4, 2, false, 0, true)               \
-  X(4, 4, 3, true, 0, true) X(8, 4, 2, true, 0, true) X(4, 8, 2, true, 0, true)
+  TRIOSEQ_PK_PLAIN(X, 0) TRIOSEQ_PK_PLAIN(X, 1) TRIOSEQ_PK_PLAIN(X, 2)                            \
+  X(4, 4, 2, 0, false, 1, false) X(4, 4, 2, 0, false, 0, true) X(4, 4, 3, 0, true, 0, true)       \
+  X(8, 4, 2, 0, true, 0, true) X(4, 8, 2, 0, true, 0, true)
+#define TRIOSEQ_PK_MATCH(r, c, w, k, x, d) \
+  (ks.rj == r && ks.rk == c && ks.wpe == w && kind == k && ks.xch == x && ks.dma == d)
 
-bool pk_shape_supported(const KernelShape& ks) {
-#define X(r, c, w, f, x, d) \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w && ks.xch == x && ks.dma == d) return true;
+bool pk_shape_supported(const KernelShape& ks, int kind) {
+#define X(r, c, w, k, f, x, d) \
+  if (TRIOSEQ_PK_MATCH(r, c, w, k, x, d)) return true;
   TRIOSEQ_PK_SHAPES(X)
 #undef X
   return false;
 }
 
-hipError_t launch_sweep_pk(const KernelShape& ks, const SweepArgs& a, const int* pk_top, const int* pk_left,
-                           uint32_t base, int grid, hipStream_t s) {
+hipError_t launch_sweep_pk(const KernelShape& ks, int kind, const SweepArgs& a, const int* pk_top,
+                           const int* pk_left, uint32_t base, uint32_t kc, int grid, hipStream_t s) {
   const size_t lds = (size_t)(a.lds_n0 + 64) * 4;
-#define X(r, c, w, f, x, d)                                                                        \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w && ks.xch == x && ks.dma == d) {                     \
-    hipLaunchKernelGGL((k_sweep_pk<r, c, w, f, x, d>), dim3(grid), dim3(64), lds, s, a, pk_top,    \
-                       pk_left, base);                                                             \
+#define X(r, c, w, k, f, x, d)                                                                     \
+  if (TRIOSEQ_PK_MATCH(r, c, w, k, x, d)) {                                                        \
+    hipLaunchKernelGGL((k_sweep_pk<r, c, w, k, f, x, d>), dim3(grid), dim3(64), lds, s, a, pk_top, \
+                       pk_left, base, kc);                                                         \
     return hipGetLastError();                                                                      \
   }
   TRIOSEQ_PK_SHAPES(X)
@@ -1833,15 +1975,16 @@ hipError_t launch_sweep_pk(const KernelShape& ks, const SweepArgs& a, const int*
   return hipErrorInvalidValue;
 }
 
-hipError_t sweep_pk_occupancy(const KernelShape& ks, uint32_t lds_n0, int* blocks_per_cu) {
-#define X(r, c, w, f, x, d)                                                                        \
-  if (ks.rj == r && ks.rk == c && ks.wpe == w && ks.xch == x && ks.dma == d)                       \
+hipError_t sweep_pk_occupancy(const KernelShape& ks, int kind, uint32_t lds_n0, int* blocks_per_cu) {
+#define X(r, c, w, k, f, x, d)                                                                     \
+  if (TRIOSEQ_PK_MATCH(r, c, w, k, x, d))                                                          \
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                           \
-        blocks_per_cu, k_sweep_pk<r, c, w, f, x, d>, 64, (size_t)(lds_n0 + 64) * 4);
+        blocks_per_cu, k_sweep_pk<r, c, w, k, f, x, d>, 64, (size_t)(lds_n0 + 64) * 4);
   TRIOSEQ_PK_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
+#undef TRIOSEQ_PK_MATCH
 
 hipError_t launch_fill_packed_sentinel(uint32_t* p, uint64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, s, p, n, kSentP * 0x10001u);

@@ -144,3 +144,97 @@ def test_packed_range_limit_falls_back_to_int32(torch_cuda):
         outs, info = run(torch_cuda, trips, sc=sc)
         assert info["packed"] == packed
         assert (outs[0] == oracle_scores(trips, sub, -2)).all()
+
+
+# Semi-global and local scoring in packed pairs (paper, Section II: the
+# initialisation and the value of v): each triplet of a pair keeps its own
+# padding, floors and last faces, so pairs of unequal shapes are the cases
+# that matter.
+KINDS = [("semi-global", ts.SEMI_GLOBAL, oracle.SEMI_GLOBAL), ("local", ts.LOCAL, oracle.LOCAL)]
+KIND_IDS = [k[0] for k in KINDS]
+
+
+def kind_scores(trips, okind, sub=oracle.DEFAULT_SUB, gap=oracle.DEFAULT_GAP):
+    return np.asarray(oracle.score_batch(trips, sub, gap, kind=okind), dtype=np.int64)
+
+
+def related(rng, count, lo, hi):
+    return [synth.mutated_triplet(rng, int(rng.integers(lo, hi + 1)), float(rng.uniform(0.02, 0.3)))
+            for _ in range(count)]
+
+
+@pytest.mark.parametrize("seed,count,max_len", [(51, 57, 40), (52, 160, 150), (53, 3, 9), (54, 31, 260)])
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_packed_kinds_equal_oracle(torch_cuda, name, kind, okind, seed, count, max_len):
+    # Fuzz (empty, one-residue and skewed sequences) plus mutated-ancestor
+    # triplets (large local and semi-global scores), shuffled so that pairs
+    # join unrelated shapes.
+    rng = np.random.default_rng(seed)
+    trips = synth.fuzz(seed=seed, count=count, max_len=max_len) + related(rng, count, 1, max_len)
+    trips = [trips[p] for p in rng.permutation(len(trips))]
+    want = kind_scores(trips, okind)
+    say(f"packed {name} seed={seed} n={len(trips)}")
+    outs, info = run(torch_cuda, trips, sc=ts.scoring(kind=kind), reps=2)
+    assert info["packed"] == 1
+    for got in outs:
+        bad = np.flatnonzero(got != want)
+        assert bad.size == 0, [(int(q), [s.size for s in trips[q]], int(got[q]), int(want[q])) for q in bad[:5]]
+
+
+@pytest.mark.parametrize("tile,wpe", PK_SHAPES)
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_packed_kinds_shapes(torch_cuda, name, kind, okind, tile, wpe):
+    rng = np.random.default_rng(55)
+    trips = synth.fuzz(seed=55, count=60, max_len=120) + related(rng, 60, 1, 140)
+    want = kind_scores(trips, okind)
+    say(f"packed {name} tile={tile} wpe={wpe}")
+    outs, info = run(torch_cuda, trips, sc=ts.scoring(kind=kind), packed=2, tile=tile, wpe=wpe)
+    assert info["packed"] == 1 and (info["tile_rows"], info["tile_cols"]) == tile
+    assert (outs[0] == want).all()
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_packed_kinds_other_scorings(torch_cuda, name, kind, okind):
+    # Random symmetric matrices with every term sub - 2*gap >= 0 (one of
+    # exactly 0), at two gaps; then a gap of 0 with a negative term (int32).
+    rng = np.random.default_rng(56)
+    trips = synth.fuzz(seed=56, count=50, max_len=80) + related(rng, 50, 1, 90)
+    for gap, packed in ((-3, 1), (-1, 1), (0, 0)):
+        m = rng.integers(-2, 5, size=(4, 4))
+        sub = np.triu(m) + np.triu(m, 1).T
+        if gap == -1:
+            sub[1, 1] = -2
+        sc = ts.scoring(sub=sub.tolist(), gap=gap, kind=kind)
+        want = kind_scores(trips, okind, sub.tolist(), gap)
+        say(f"packed {name} scoring gap={gap}")
+        outs, info = run(torch_cuda, trips, sc=sc)
+        assert info["packed"] == packed, (gap, sub - 2 * gap)
+        assert (outs[0] == want).all()
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_packed_kinds_equal_int32_and_alone(torch_cuda, name, kind, okind):
+    rng = np.random.default_rng(57)
+    trips = related(rng, 41, 20, 200)
+    sc = ts.scoring(kind=kind)
+    pk, info_pk = run(torch_cuda, trips, sc=sc)
+    i32, info_32 = run(torch_cuda, trips, sc=sc, packed=1)
+    assert info_pk["packed"] == 1 and info_32["packed"] == 0
+    assert (pk[0] == i32[0]).all()
+    perm = rng.permutation(len(trips))
+    shuffled, _ = run(torch_cuda, [trips[p] for p in perm], sc=sc)
+    assert (shuffled[0] == pk[0][perm]).all()
+    for q in range(0, len(trips), 8):
+        assert ts.score(trips[q], sc) == pk[0][q]
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_packed_kinds_graph_replays(torch_cuda, name, kind, okind):
+    rng = np.random.default_rng(58)
+    trips = related(rng, 70, 10, 180)
+    want = kind_scores(trips, okind)
+    say(f"packed {name} graph")
+    outs, info = run(torch_cuda, trips, sc=ts.scoring(kind=kind), use_graph=True, reps=3)
+    assert info["packed"] == 1
+    for got in outs:
+        assert (got == want).all()
