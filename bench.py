@@ -66,13 +66,13 @@ TRAFFIC = {
 
 def scoring_path(trips, kind: str, engine: int, tile: str, packed: bool = False) -> str:
     """Which kernels a plan runs: "halves" (a lone global triplet whose longest
-    sequence has at least 256 residues, automatic engine, 4x4 tiles: its two halves swept
+    sequence has at least 128 residues, automatic engine, 4x4 tiles: its two halves swept
     concurrently with the last-slice plane variant, then met), "split" (panel
     jobs), "batch" (several triplets) or "batch-packed" (several triplets, two
     per lane in 16-bit halves)."""
     if len(trips) != 1:
         return "batch-packed" if packed else "batch"
-    if kind == "global" and engine == -1 and tile in ("0x0", "4x4") and max(s.size for s in trips[0]) >= 256:
+    if kind == "global" and engine == -1 and tile in ("0x0", "4x4") and max(s.size for s in trips[0]) >= 128:
         return "halves"
     return "split"
 
@@ -505,6 +505,7 @@ def main():
                                       "packed": b["packed"] == 2,
                                       "lane_exchange": "registers" if b["lane_exchange"] == 2 else "lds",
                                       "split_factor": b["split_factor"] or 4,
+                                      "staging": "lds-direct" if b["staging"] == 2 else "registers",
                                       "tried": tuned["tried"], "rejected": tuned["rejected"]}
     if len(trips) > 1 and args.per_triplet_sample > 0:
         rec["per_triplet_path"] = per_triplet(ts, torch, trips, args.per_triplet_sample, stream,

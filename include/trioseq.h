@@ -209,13 +209,13 @@ typedef struct trioseq_plan_options {
                              mean cells per wavefront (or 2.5e8); 0 = default (4) */
   int32_t half_split_min; /* automatic engine, one global triplet: scored by two
                              concurrent halves when its longest sequence has at least
-                             this many residues; -1 = never; 0 = default (256) */
+                             this many residues; -1 = never; 0 = default (128) */
   int32_t packed;         /* 1 = int32 lanes; 2 = two triplets per lane, 16 bits each
-                             (global scoring of batches of whole triplets whose
-                             substitution terms sub - 2*gap are all >= 0 and whose
-                             values fit the 16-bit range; exact, like the int32 path;
-                             a batch that does not qualify runs in int32); 0 = default
-                             (2 when the lane tile is left to the library, else 1) */
+                             (batches of whole triplets, any kind, whose substitution
+                             terms sub - 2*gap are all >= 0 and whose values fit the
+                             16-bit range; exact, like the int32 path; a batch that
+                             does not qualify runs in int32); 0 = default (2 when the
+                             lane tile is left to the library, else 1) */
   int32_t staging;        /* packed pairs: 1 = face rows staged through registers into
                              LDS; 2 = loaded straight into LDS (buffer loads to LDS);
                              0 = default */

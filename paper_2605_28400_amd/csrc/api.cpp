@@ -395,13 +395,34 @@ static bool pair_up(Layout* L, const trioseq_scoring& sc, const KernelShape& ks)
     }
   if (mina < 0 || maxa > 255 || !pk_shape_supported(ks, sc.kind)) return false;
   const int H = panel_rows(ks), W = panel_cols(ks), RR = (int)right_face_row(ks);
-  std::vector<size_t> idx(n);
+  const size_t np = (n + 1) / 2;
+  // A pair costs the panels of its common grid times its steps. Neighbours
+  // in two sort orders are paired, and the cheaper pairing is kept: by the
+  // lengths (similar sweep lengths), or by the panel counts of the other two
+  // axes first (no pair crosses a panel boundary the two do not share).
+  auto pair_cost = [&](const TripletDesc& a, const TripletDesc& b) {
+    const uint64_t n0 = std::max(a.len[0], b.len[0]);
+    const uint64_t PJ = std::max(a.len[1], b.len[1]) / H + 1, PK = std::max(a.len[2], b.len[2]) / W + 1;
+    return PJ * PK * (n0 + 1 + kSkew);
+  };
+  auto total_cost = [&](const std::vector<size_t>& v) {
+    uint64_t c = 0;
+    for (size_t q = 0; q < np; ++q) c += pair_cost(L->desc[v[2 * q]], L->desc[v[std::min(2 * q + 1, n - 1)]]);
+    return c;
+  };
+  std::vector<size_t> idx(n), idx2(n);
   std::iota(idx.begin(), idx.end(), 0);
+  std::iota(idx2.begin(), idx2.end(), 0);
   std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
     const TripletDesc &da = L->desc[a], &db = L->desc[b];
     return std::make_tuple(da.len[0], da.len[1], da.len[2]) < std::make_tuple(db.len[0], db.len[1], db.len[2]);
   });
-  const size_t np = (n + 1) / 2;
+  std::stable_sort(idx2.begin(), idx2.end(), [&](size_t a, size_t b) {
+    const TripletDesc &da = L->desc[a], &db = L->desc[b];
+    return std::make_tuple(da.len[1] / H, da.len[2] / W, da.len[0], da.len[1], da.len[2]) <
+           std::make_tuple(db.len[1] / H, db.len[2] / W, db.len[0], db.len[1], db.len[2]);
+  });
+  if (total_cost(idx2) < total_cost(idx)) idx.swap(idx2);
   uint64_t box_jk = 0, n0max = 0, stride = 0;
   std::vector<uint64_t> cost(np);
   for (size_t q = 0; q < np; ++q) {
@@ -413,7 +434,7 @@ static bool pair_up(Layout* L, const trioseq_scoring& sc, const KernelShape& ks)
     box_jk = std::max(box_jk, PJ * H + PK * W);
     n0max = std::max<uint64_t>(n0max, n0);
     stride = std::max(stride, rows * (PK * W + RR));
-    cost[q] = PJ * PK * (uint64_t)(n0 + 1 + kSkew);
+    cost[q] = pair_cost(a, b);
   }
   // Real values: base + M' with M' <= mx per unit of index sum (a move adds
   // at most one term per residue it consumes; the local floor and the
@@ -722,7 +743,7 @@ trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested
 // over that plane (the crossing identity Hirschberg's method rests on). Each
 // half's pipeline of panels is as long as the whole triplet's but sweeps half
 // the slices, and the two fill together: the lone triplet finishes sooner.
-constexpr uint32_t kHalfSplitMin = 256;  // shortest longest-sequence for it
+constexpr uint32_t kHalfSplitMin = 128;  // shortest longest-sequence for it
 struct HalfSplit {
   uint32_t lens[6];
   uint64_t offs[6];      // word offsets in the gathered buffer

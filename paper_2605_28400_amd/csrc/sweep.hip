@@ -178,6 +178,15 @@ __device__ __forceinline__ uint32_t opaque_zero() {
 typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 
+// Four consecutive ints of LDS starting on a 16-byte boundary, read as one
+// 128-bit access. A lane's halo row is either a ring row or a neighbour's
+// slot row; both are 16-byte aligned, but the compiler cannot see that
+// through the choice and would split the read into 8-byte halves, whose
+// 16-byte lane stride makes lanes 8 apart collide on one LDS bank.
+__device__ __forceinline__ v4i lds_v4(const int* p) {
+  return *reinterpret_cast<const v4i*>(__builtin_assume_aligned(p, 16));
+}
+
 // Per-slice lookup shifts: shb[i + kShiftPre] = 8 * code(S0[i-1]) for slices
 // 1..n0, 0 elsewhere; covers slices -kShiftPre .. n0 + 47.
 __device__ __forceinline__ void stage_shifts(uint8_t* shb, const uint32_t* __restrict__ words,
@@ -611,10 +620,17 @@ __device__ int sweep_panel(Lds<RJ, RK>& L, const uint8_t* shb, const DevScoring&
       int T[RK], Lh[RJ];
       const int* tp = tb + s * t_str;
       const int* lp = lb + s * l_str;
+      static_assert(RJ % 4 == 0 && RK % 4 == 0, "halo rows are read 4 entries at a time");
 #pragma unroll
-      for (int cc = 0; cc < RK; ++cc) T[cc] = tp[cc];
+      for (int cc = 0; cc < RK; cc += 4) {
+        const v4i v = lds_v4(tp + cc);
+        T[cc] = v.x, T[cc + 1] = v.y, T[cc + 2] = v.z, T[cc + 3] = v.w;
+      }
 #pragma unroll
-      for (int r = 0; r < RJ; ++r) Lh[r] = lp[r];
+      for (int r = 0; r < RJ; r += 4) {
+        const v4i v = lds_v4(lp + r);
+        Lh[r] = v.x, Lh[r + 1] = v.y, Lh[r + 2] = v.z, Lh[r + 3] = v.w;
+      }
       int corner = cb[s * c_str];
       if (XCH) {
         // The upper and left neighbours finished this lane's slice one step
@@ -1633,9 +1649,15 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
       for (int cc = 0; cc < RK; ++cc) B[cc] = __builtin_amdgcn_perm(TCb[cc], TCa[cc], sv);
       uint32_t T[RK], Lh[RJ];
 #pragma unroll
-      for (int cc = 0; cc < RK; ++cc) T[cc] = (uint32_t)tb[s * t_str + cc];
+      for (int cc = 0; cc < RK; cc += 4) {
+        const v4i v = lds_v4(tb + s * t_str + cc);
+        T[cc] = (uint32_t)v.x, T[cc + 1] = (uint32_t)v.y, T[cc + 2] = (uint32_t)v.z, T[cc + 3] = (uint32_t)v.w;
+      }
 #pragma unroll
-      for (int r = 0; r < RJ; ++r) Lh[r] = (uint32_t)lb[s * l_str + r];
+      for (int r = 0; r < RJ; r += 4) {
+        const v4i v = lds_v4(lb + s * l_str + r);
+        Lh[r] = (uint32_t)v.x, Lh[r + 1] = (uint32_t)v.y, Lh[r + 2] = (uint32_t)v.z, Lh[r + 3] = (uint32_t)v.w;
+      }
       uint32_t corner = (uint32_t)cbp[s * c_str];
       if (XCH) {
         // As in sweep_panel: inner lanes take their upper neighbour's row

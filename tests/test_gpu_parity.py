@@ -144,6 +144,11 @@ def test_single_128_matches_golden(torch_cuda):
     assert ts.score(w.triplets[0]) == g["scores"][0]
     got, _ = run_plan(torch_cuda, w.triplets, engine=0)
     assert int(got[0]) == g["scores"][0]
+    # The default options (scored by halves at this length), as the benchmark
+    # times them: graph replays.
+    outs, info = run_plan(torch_cuda, w.triplets, engine=-1, use_graph=True, reps=3)
+    assert info["engine"] == 1 and info["panels"] == 50
+    assert all(int(o[0]) == g["scores"][0] for o in outs)
 
 
 def test_single_1k_matches_golden(torch_cuda):
