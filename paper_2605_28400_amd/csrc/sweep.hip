@@ -1429,13 +1429,36 @@ __device__ __forceinline__ void stage_selectors(uint32_t* sel, const uint32_t* _
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
 }
 
+// LDS of a packed wavefront: the lanes' edge slots and the capture tile
+// (one object), and the halo rings, one object per chunk half. Staging of
+// chunk c + 1 goes to the half that chunk c does not read; as two distinct
+// objects the compiler can tell that the loads into one half never alias
+// the reads of the other, and so does not make those reads wait for the
+// loads (as it must within one object).
+template <int RJ, int RK>
+struct PkLds {
+  __attribute__((aligned(16))) int sR[64][RJ];  // right column of each lane
+  __attribute__((aligned(16))) int sB[64][RK];  // bottom row of each lane
+  int sX[64];                                   // bottom of each lane's left halo
+  int cap[RJ * RK];                             // tile of triplet a's score cell
+  int wsync;
+};
+template <int RJ, int RK>
+struct PkRing {
+  static constexpr int H = kGJ * RJ, W = kGK * RK;
+  __attribute__((aligned(16))) int T[kChunk][W];    // top face rows of the chunk
+  __attribute__((aligned(16))) int C[kChunk][kGK];  // corners of the top-edge lanes
+  __attribute__((aligned(16))) int L[kChunk][H];    // left face rows of the chunk
+};
+
 // One panel of a pair (plain faces in the wave's workspace, one 32-bit word
 // per entry holding both halves). Global scoring captures each triplet's
 // cell (n0, n1, n2) when the panel holds it: triplet a's tile into L.cap,
 // b's into capb. Semi-global and local scoring fold the panel's cells into
 // the lane's running best (both halves; see k_sweep_pk for its meaning).
 template <int RJ, int RK, int KIND, bool FUSED, int XCH, bool DMA>
-__device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, const DevScoring& sc,
+__device__ void sweep_panel_pk(PkLds<RJ, RK>& L, PkRing<RJ, RK>& R0, PkRing<RJ, RK>& R1, int* capb,
+                               const uint32_t* sel, const DevScoring& sc,
                                const uint32_t* __restrict__ words, const TripletDesc& ta,
                                const TripletDesc& tb, int n0, int pj, int pk, const int* top, const int* left,
                                int* bot, int* right, uint32_t base2, uint32_t& best, uint32_t kc) {
@@ -1545,26 +1568,25 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
   const int eL = lane % H;
   const uint32_t offL = (uint32_t)((kGK - 1 + lane / H) * (int)RRB + (4 + eL) * 4);
   int pf[DMA ? 1 : NPF];
-  auto stage_load = [&](int c) {
+  auto stage_load = [&](int c, PkRing<RJ, RK>& dst) {
     const uint32_t cb0 = (uint32_t)(c * kChunk);
     if (DMA) {
       // Straight into the ring half of chunk c (lane l's word of each load
       // lands at the destination + 4 l, which is where it belongs); the
       // corner loads go to the same slots from the top or the left face,
       // so each lane takes only one of them.
-      const int rr = (c & 1) * kChunk;
       typedef __attribute__((address_space(3))) void* LdsPtr;
 #pragma unroll
       for (int q = 0; q < QT; ++q)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_top, (LdsPtr)(&L.ringT[rr][0] + 64 * q), 4, offT,
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_top, (LdsPtr)(&dst.T[0][0] + 64 * q), 4, offT,
                                                  (cb0 + q * RT) * ts, 0, 0);
       if (corner_from_left)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_left, (LdsPtr)&L.ringC[rr][0], 4, offC, cb0 * RRB, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_left, (LdsPtr)&dst.C[0][0], 4, offC, cb0 * RRB, 0, 0);
       else
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_top, (LdsPtr)&L.ringC[rr][0], 4, offC, cb0 * ts, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_top, (LdsPtr)&dst.C[0][0], 4, offC, cb0 * ts, 0, 0);
 #pragma unroll
       for (int q = 0; q < QL; ++q)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_left, (LdsPtr)(&L.ringL[rr][0] + 64 * q), 4, offL,
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r_left, (LdsPtr)(&dst.L[0][0] + 64 * q), 4, offL,
                                                  (cb0 + q * RL) * RRB, 0, 0);
       return;
     }
@@ -1581,25 +1603,35 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
       }
     }
   };
-  auto stage_finish = [&](int c) {
+  auto stage_finish = [&](int c, PkRing<RJ, RK>& dst) {
     if (DMA) {
-      // The loads of chunk c were issued a chunk earlier: wait for them
-      // (vmcnt counts them with the stores issued since, so wait for all).
-      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      // The loads of chunk c were issued at the first step of chunk c - 1,
+      // ahead of that chunk's face stores (kStores per step); vector memory
+      // operations complete in issue order, so once no more than those
+      // stores are outstanding the loads are done, and the stores need not
+      // be waited for. Chunk 0's loads were issued just before, with no
+      // store after them.
+      constexpr int kStores = RK / 4 + RJ / 4 + 1;
+      constexpr int kAfter = kStores * kChunk;
+      static_assert(kAfter < 64, "vmcnt holds at most 63");
+      constexpr int kWaitAfter = (kAfter & 15) | ((kAfter >> 4) << 14) | (0x7 << 4) | (0xF << 8);
+      if (c == 0)
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      else
+        __builtin_amdgcn_s_waitcnt(kWaitAfter);  // vmcnt(kAfter)
       return;
     }
-    const int rr = (c & 1) * kChunk;
 #pragma unroll
     for (int q = 0; q < NPF; ++q) {
       if (q < QT)
-        (&L.ringT[rr][0])[lane + 64 * q] = pf[q];
+        (&dst.T[0][0])[lane + 64 * q] = pf[q];
       else if (q < QT + QC)
-        L.ringC[rr][lane] = pf[q];
+        dst.C[0][lane] = pf[q];
       else
-        (&L.ringL[rr][0])[lane + 64 * (q - QT - QC)] = pf[q];
+        (&dst.L[0][0])[lane + 64 * (q - QT - QC)] = pf[q];
     }
   };
-  stage_load(0);
+  stage_load(0, R0);
 #pragma unroll
   for (int r = 0; r < RJ; ++r) L.sR[lane][r] = (int)(kSentP * 0x10001u);
 #pragma unroll
@@ -1608,11 +1640,13 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
 
   const bool y0 = y == 0, x0 = x == 0;
   const bool tring = XCH || y0, lring = XCH || x0;
-  const int* t_base = tring ? &L.ringT[0][x * RK] : &L.sB[y0 ? 0 : lane - 8][0];
+  // Halo rows: edge lanes read the chunk's ring half, inner lanes their
+  // neighbour's slot (the same every step).
+  const int* t_slot = &L.sB[y0 ? 0 : lane - 8][0];
   const int t_str = tring ? W : 0;
-  const int* c_base = tring ? &L.ringC[0][x] : &L.sX[y0 ? 0 : lane - 8];
+  const int* c_slot = &L.sX[y0 ? 0 : lane - 8];
   const int c_str = tring ? kGK : 0;
-  const int* l_base = lring ? &L.ringL[0][y * RJ] : &L.sR[x0 ? 0 : lane - 1][0];
+  const int* l_slot = &L.sR[x0 ? 0 : lane - 1][0];
   const int l_str = lring ? H : 0;
   const int up_addr = ((lane + 64 - kGK) & 63) << 2;
   const uint32_t vo_bot = (y == kGJ - 1) ? (uint32_t)(x * RK * 4) : kOob;
@@ -1621,25 +1655,27 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
   const int sl_base = kShiftPre - y - x;
   const bool seed_lane = pj == 0 && pk == 0 && lane == 0;
 
-  for (int c = 0; c < nchunks; ++c) {
-    stage_finish(c);
+  // Chunk c reads ring half cur and stages chunk c + 1 into nxt. With loads
+  // straight to LDS the loop below takes two chunks per turn, so that both
+  // halves are fixed objects in each copy of the body.
+  auto run_chunk = [&](int c, PkRing<RJ, RK>& cur, PkRing<RJ, RK>& nxt) __attribute__((always_inline)) {
+    stage_finish(c, cur);
     const bool more = c + 1 < nchunks;
     const int cb0 = c * kChunk;
     const bool cap_chunk = (n0a >= cb0 - kSkew && n0a <= cb0 + kChunk - 1) ||
                            (n0b >= cb0 - kSkew && n0b <= cb0 + kChunk - 1);
     const uint32_t vb = vo_bot + (uint32_t)cb0 * ts, vr = vo_right + (uint32_t)cb0 * RRB,
                    vc = vo_corner + (uint32_t)cb0 * RRB;
-    const int rr = (c & 1) * kChunk;
-    const int* tb = t_base + rr * t_str;
-    const int* cbp = c_base + rr * c_str;
-    const int* lb = l_base + rr * l_str;
+    const int* tb = tring ? &cur.T[0][x * RK] : t_slot;
+    const int* cbp = tring ? &cur.C[0][x] : c_slot;
+    const int* lb = lring ? &cur.L[0][y * RJ] : l_slot;
     const uint32_t* sp = sel + sl_base + cb0;
     uint32_t selv[kChunk];
 #pragma unroll
     for (int s = 0; s < kChunk; ++s) selv[s] = sp[s];
 #pragma unroll
     for (int s = 0; s < kChunk; ++s) {
-      if (s == 0 && more) stage_load(c + 1);
+      if (s == 0 && more) stage_load(c + 1, nxt);
       const int t = cb0 + s;
       const uint32_t sv = selv[s];
       uint32_t A[RJ], B[RK];
@@ -1826,6 +1862,16 @@ __device__ void sweep_panel_pk(Lds<RJ, RK>& L, int* capb, const uint32_t* sel, c
 #pragma unroll
       for (int cc = 0; cc < RK; ++cc) Tp[cc] = T[cc];
     }
+  };
+  if constexpr (DMA) {
+    for (int c = 0; c < nchunks; c += 2) {
+      run_chunk(c, R0, R1);
+      if (c + 1 < nchunks) run_chunk(c + 1, R1, R0);
+    }
+  } else {
+    // Staged through registers, the rings are written by LDS stores, which
+    // need no such care; one copy of the body keeps register pressure down.
+    for (int c = 0; c < nchunks; ++c) run_chunk(c, (c & 1) ? R1 : R0, (c & 1) ? R0 : R1);
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
 }
@@ -1841,7 +1887,8 @@ template <int RJ, int RK, int WPE, int KIND, bool FUSED, int XCH, bool DMA>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_sweep_pk(SweepArgs a, const int* pk_top, const int* pk_left, uint32_t base, uint32_t kc) {
   constexpr int H = kGJ * RJ, W = kGK * RK;
-  __shared__ Lds<RJ, RK> L;
+  __shared__ PkLds<RJ, RK> L;
+  __shared__ PkRing<RJ, RK> R0, R1;
   __shared__ int capb[RJ * RK];
   extern __shared__ uint32_t selw[];
   int* face = a.face + (uint64_t)blockIdx.x * a.face_stride;
@@ -1867,7 +1914,7 @@ k_sweep_pk(SweepArgs a, const int* pk_top, const int* pk_left, uint32_t base, ui
     for (int pj = 0; pj < PJ; ++pj) {
       for (int pk = 0; pk < PK; ++pk) {
         int* col = fb + (uint64_t)pk * rows * W;
-        sweep_panel_pk<RJ, RK, KIND, FUSED, XCH, DMA>(L, capb, selw, a.sc, a.words, ta, tb, n0, pj, pk,
+        sweep_panel_pk<RJ, RK, KIND, FUSED, XCH, DMA>(L, R0, R1, capb, selw, a.sc, a.words, ta, tb, n0, pj, pk,
                                                       pj ? col : pk_top, pk ? fr : pk_left,
                                                       pj + 1 < PJ ? col : nullptr, pk + 1 < PK ? fr : nullptr,
                                                       base2, best, kc);
