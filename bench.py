@@ -50,10 +50,12 @@ WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served", "tr
 # Keyed by (workload, kind, lane tile, path): the autotuner may pick another
 # tile, and a lone global triplet under automatic options is scored by halves.
 TRAFFIC = {
-    ("batch_8192_len100-400", "global", "4x4", "batch-packed"): (4.9159e10, "249ee33828e878c3"),
-    ("single_1024x1000x1048", "global", "4x4", "halves"): (1.5490e9, "249ee33828e878c3"),
-    ("single_4096x4000x4150", "global", "4x4", "halves"): (7.7832e10, "249ee33828e878c3"),
-    ("single_128x128x128", "global", "4x4", "split"): (5.2664e6, "249ee33828e878c3"),
+    ("batch_8192_len100-400", "global", "4x4", "batch-packed+lds-direct"): (4.8535e10, "52a5a7416be419c9"),
+    ("batch_8192_len100-400", "local", "4x4", "batch-packed"): (4.8465e10, "52a5a7416be419c9"),
+    ("batch_8192_len100-400", "semi-global", "4x4", "batch-packed"): (4.8559e10, "52a5a7416be419c9"),
+    ("single_1024x1000x1048", "global", "4x4", "halves"): (1.5199e9, "52a5a7416be419c9"),
+    ("single_4096x4000x4150", "global", "4x4", "halves"): (7.7791e10, "52a5a7416be419c9"),
+    ("single_128x128x128", "global", "4x4", "halves"): (5.9279e6, "52a5a7416be419c9"),
     ("batch_8192_len100-400", "global", "8x4", "batch"): (7.2410e10, "5b986628d09c52c4"),
     ("single_1024x1000x1048", "global", "4x4", "split"): (1.5689e9, "5b986628d09c52c4"),
     ("single_4096x4000x4150", "global", "4x4", "split"): (7.9174e10, "5b986628d09c52c4"),
@@ -417,6 +419,9 @@ def main():
     path = scoring_path(trips, args.kind, args.engine, args.tile, packed)
     if packed:
         ops = OPS_PER_CELL_PACKED_OF[args.kind]
+        # The plan takes the autotuner's choice, staging included.
+        if tuned is not None and tuned["best"]["staging"] == 2:
+            path += "+lds-direct"
     d_scores = torch.zeros(len(trips), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 
