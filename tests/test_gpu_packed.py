@@ -242,3 +242,21 @@ def test_packed_kinds_graph_replays(torch_cuda, name, kind, okind):
     assert info["packed"] == 1
     for got in outs:
         assert (got == want).all()
+
+
+@pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
+def test_packed_kinds_range_limit_falls_back_to_int32(torch_cuda, name, kind, okind):
+    # A gap of -6 makes the local floor and the semi-global axes grow by 12
+    # per residue: ~500-residue sequences could pass the 16-bit range, so the
+    # batch runs in int32 lanes; the same scoring on short sequences runs
+    # packed. Both give the oracle's scores.
+    sub = [[1 if x == y else -1 for y in range(4)] for x in range(4)]
+    sc = ts.scoring(sub=sub, gap=-6, kind=kind)
+    rng = np.random.default_rng(62)
+    long = [synth.mutated_triplet(rng, 500, 0.1), synth.mutated_triplet(rng, 40, 0.1)]
+    short = related(rng, 6, 30, 70)
+    for trips, packed in ((long, 0), (short, 1)):
+        say(f"packed {name} range limit packed={packed}")
+        outs, info = run(torch_cuda, trips, sc=sc)
+        assert info["packed"] == packed
+        assert (outs[0] == kind_scores(trips, okind, sub, -6)).all()
