@@ -1431,10 +1431,11 @@ __device__ __forceinline__ void stage_selectors(uint32_t* sel, const uint32_t* _
 
 // LDS of a packed wavefront: the lanes' edge slots and the capture tile
 // (one object), and the halo rings, one object per chunk half. Staging of
-// chunk c + 1 goes to the half that chunk c does not read; as two distinct
-// objects the compiler can tell that the loads into one half never alias
-// the reads of the other, and so does not make those reads wait for the
-// loads (as it must within one object).
+// chunk c + 1 goes to the half that chunk c does not read. Kept as two
+// objects, each a fixed object in its copy of the chunk body, the halves
+// take static addresses. (The compiler still makes a chunk's first halo
+// read wait for the loads in flight, since a lane's read picks between a
+// ring row and a slot; the other wave on the SIMD covers that wait.)
 template <int RJ, int RK>
 struct PkLds {
   __attribute__((aligned(16))) int sR[64][RJ];  // right column of each lane
