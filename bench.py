@@ -48,7 +48,8 @@ WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served", "tr
 # with the commands are under profiles/). Each figure holds only for the kernel
 # source it was measured on; for any other source the field is null.
 # Keyed by (workload, kind, lane tile, path): the autotuner may pick another
-# tile, and a lone global triplet under automatic options is scored by halves.
+# tile, and a lone global or local triplet under automatic options is scored by
+# halves.
 TRAFFIC = {
     ("batch_8192_len100-400", "global", "4x4", "batch-packed+lds-direct"): (4.8537e10, "59f5c7ff675def0d"),
     ("batch_8192_len100-400", "local", "4x4", "batch-packed"): (4.8458e10, "59f5c7ff675def0d"),
@@ -56,6 +57,7 @@ TRAFFIC = {
     ("single_1024x1000x1048", "global", "4x4", "halves"): (1.5221e9, "59f5c7ff675def0d"),
     ("single_4096x4000x4150", "global", "4x4", "halves"): (7.7787e10, "59f5c7ff675def0d"),
     ("single_128x128x128", "global", "4x4", "halves"): (5.9224e6, "59f5c7ff675def0d"),
+    ("single_1024x1000x1048", "local", "4x4", "halves"): (1.6290e9, "121dba023671257b"),
     ("batch_8192_len100-400", "global", "8x4", "batch"): (7.2410e10, "5b986628d09c52c4"),
     ("single_1024x1000x1048", "global", "4x4", "split"): (1.5689e9, "5b986628d09c52c4"),
     ("single_4096x4000x4150", "global", "4x4", "split"): (7.9174e10, "5b986628d09c52c4"),
@@ -68,13 +70,15 @@ TRAFFIC = {
 
 def scoring_path(trips, kind: str, engine: int, tile: str, packed: bool = False) -> str:
     """Which kernels a plan runs: "halves" (a lone global triplet whose longest
-    sequence has at least 128 residues, automatic engine, 4x4 tiles: its two halves swept
-    concurrently with the last-slice plane variant, then met), "split" (panel
-    jobs), "batch" (several triplets) or "batch-packed" (several triplets, two
-    per lane in 16-bit halves)."""
+    sequence has at least 128 residues, or a local one with 128 to 2047, automatic
+    engine, 4x4 tiles: its two halves swept concurrently with the last-slice plane
+    variant, then met), "split" (panel jobs), "batch" (several triplets) or
+    "batch-packed" (several triplets, two per lane in 16-bit halves)."""
     if len(trips) != 1:
         return "batch-packed" if packed else "batch"
-    if kind == "global" and engine == -1 and tile in ("0x0", "4x4") and max(s.size for s in trips[0]) >= 128:
+    longest = max(s.size for s in trips[0])
+    if (engine == -1 and tile in ("0x0", "4x4") and longest >= 128
+            and (kind == "global" or (kind == "local" and longest < 2048))):
         return "halves"
     return "split"
 

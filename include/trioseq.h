@@ -207,9 +207,10 @@ typedef struct trioseq_plan_options {
   int32_t split_factor;   /* automatic engine: a triplet of a batch is split into panel
                              jobs when its cells exceed split_factor times the batch's
                              mean cells per wavefront (or 2.5e8); 0 = default (4) */
-  int32_t half_split_min; /* automatic engine, one global triplet: scored by two
-                             concurrent halves when its longest sequence has at least
-                             this many residues; -1 = never; 0 = default (128) */
+  int32_t half_split_min; /* automatic engine, one global or local triplet: scored by
+                             two concurrent halves when its longest sequence has at
+                             least this many residues; -1 = never; 0 = default (128,
+                             and for local scoring only below 2048 residues) */
   int32_t packed;         /* 1 = int32 lanes; 2 = two triplets per lane, 16 bits each
                              (batches of whole triplets, any kind, whose substitution
                              terms sub - 2*gap are all >= 0 and whose values fit the

@@ -743,7 +743,14 @@ trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested
 // over that plane (the crossing identity Hirschberg's method rests on). Each
 // half's pipeline of panels is as long as the whole triplet's but sweeps half
 // the slices, and the two fill together: the lone triplet finishes sooner.
-constexpr uint32_t kHalfSplitMin = 128;  // shortest longest-sequence for it
+// A local alignment either crosses the plane (the same identity, over the
+// halves' local values) or lies within one half, so its score is the best of
+// that plane maximum and the two halves' own bests. Local scoring does more
+// work per cell, so the panel grid is busy enough on its own sooner: by
+// default it takes the halves only below kHalfSplitMaxLocal residues (a
+// threshold the caller sets lifts that cap).
+constexpr uint32_t kHalfSplitMin = 128;        // shortest longest-sequence for it
+constexpr uint32_t kHalfSplitMaxLocal = 2048;  // local scoring, default threshold
 struct HalfSplit {
   uint32_t lens[6];
   uint64_t offs[6];      // word offsets in the gathered buffer
@@ -809,10 +816,15 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
   int hint = 256 * kWavesPerCuHint;
   trioseq_status st = build_layout(lens, word_off, n, *scp, o, hint, &L);
   if (st != TRIOSEQ_OK) return st;
-  // A lone global triplet under the automatic options is scored by halves.
+  // A lone global or local triplet under the automatic options is scored by
+  // halves (local: the best of the two halves' own bests and of the paths
+  // that cross the middle plane).
   HalfSplit hs;
-  const bool half = n == 1 && defaults && scp->kind == kGlobal &&
-                    half_split_layout(lens, word_off, o.half_split_min, &hs);
+  const bool half_kind =
+      scp->kind == kGlobal ||
+      (scp->kind == kLocal && o.lane_exchange != 2 &&
+       (o.half_split_min != 0 || n != 1 || std::max({lens[0], lens[1], lens[2]}) < kHalfSplitMaxLocal));
+  const bool half = n == 1 && defaults && half_kind && half_split_layout(lens, word_off, o.half_split_min, &hs);
   const trioseq_plan_options ho{-1, 4, 4, 0, 0, 2, o.panel_group, o.lane_exchange};  // the plane kernels' shape
   DeviceProps dp;
   st = device_props(&dp);
@@ -1113,19 +1125,23 @@ static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t
   if (p->n == 0) return hipSuccess;
   hipError_t e;
   if (p->half) {
-    // Gather the halves (and prepare the run), sweep both (writing their
-    // last slices), meet.
-    if ((e = launch_gather(d_words, p->d_gather, 6, p->h_words_n, p->d_hwords, p->d_ctl, p->d_counter, s)) !=
-        hipSuccess)
+    // Gather the halves (and prepare the run: the gather kernel does it when
+    // there are no reduction pairs to reset), sweep both (writing their last
+    // slices), meet. Under local scoring each half leaves its own best in
+    // d_hscores[0..1] and the meet takes them with the crossing paths' best.
+    const bool red = p->red_pairs != 0;
+    if (red && (e = launch_prepare(p->d_ctl, p->d_counter, p->d_red, p->red_pairs, s)) != hipSuccess) return e;
+    if ((e = launch_gather(d_words, p->d_gather, 6, p->h_words_n, p->d_hwords, red ? nullptr : p->d_ctl,
+                           p->d_counter, s)) != hipSuccess)
       return e;
     SweepArgs a = make_sweep_args(p->d_hwords, p->d_desc, p->d_jobs, p->njobs, p->lds_n0, p->d_hscores,
                                   p->d_counter, p->d_ctl, p->d_face, p->face_stride, p->d_pface, p->bnd,
-                                  nullptr, p->sc);
+                                  p->d_red, p->sc);
     a.plane = p->d_plane;
     a.plane_off = p->d_plane_off;
     if ((e = launch_sweep(p->ks, p->modes, a, p->grid, s)) != hipSuccess) return e;
     return launch_meet(p->d_sdesc, p->d_chunk_box, p->h_nchunk, p->d_plane, p->d_partial, p->d_ctl + 1,
-                       d_scores, s);
+                       p->sc.kind == kLocal ? p->d_hscores : nullptr, d_scores, s);
   }
   if ((e = launch_prepare(p->d_ctl, p->d_counter, p->d_red, p->red_pairs, s)) != hipSuccess)
     return e;

@@ -140,7 +140,7 @@ hipError_t sweep_occupancy(const KernelShape& ks, int modes, int kind, bool plan
                            int* waves_per_cu);
 // Whether scoring kernels of this tile shape (and lane exchange) exist for
 // this alignment kind. Plane kernels exist for 4 x 4 tiles at two waves per
-// SIMD, global kind.
+// SIMD: global kind (either lane exchange) and local kind (LDS slot arrays).
 bool shape_supported(const KernelShape& ks, int kind);
 
 // Packed pairs (two triplets per lane, 16 bits each; batches of whole
@@ -201,9 +201,12 @@ struct GatherDesc {
 hipError_t launch_gather(const uint32_t* in, const GatherDesc* d, uint32_t n, uint32_t words_out,
                          uint32_t* out, int* ctl, int* counter, hipStream_t s);
 // After launch_split's first stage over one box: out[0] = the best F + R of
-// box 0, or INT32_MIN if err[0] is set (a wait of the run gave up).
+// box 0, or INT32_MIN if err[0] is set (a wait of the run gave up). With
+// own non-null (local scoring), the best also covers own[0] and own[1], the
+// halves' own bests.
 hipError_t launch_meet(const SplitDesc* box, const uint32_t* chunk_box, uint32_t nchunks,
-                       const int* planes, int* partial, const int* err, int32_t* out, hipStream_t s);
+                       const int* planes, int* partial, const int* err, const int* own, int32_t* out,
+                       hipStream_t s);
 // out[3b] = best F + R of box b, out[3b+1], out[3b+2] = its (p, q).
 // chunk_box[c] = the box of chunk c; partial: 2 ints per chunk.
 hipError_t launch_split(const int* planes, const SplitDesc* boxes, uint32_t n, const uint32_t* chunk_box,

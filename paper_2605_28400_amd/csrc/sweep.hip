@@ -2003,7 +2003,8 @@ __global__ void k_prepare(int* ctl, int* counter, int* red, uint32_t nred) {
 #define TRIOSEQ_SHAPES(X)                                                                        \
   X(4, 4, 4, 0, false, 0) X(4, 4, 2, 0, false, 0) X(8, 4, 2, 0, false, 0) X(4, 8, 2, 0, false, 0) \
   X(4, 4, 2, 1, false, 0) X(4, 4, 2, 2, false, 0) X(8, 4, 2, 1, false, 0) X(8, 4, 2, 2, false, 0) \
-  X(4, 4, 2, 0, true, 0) X(4, 4, 2, 0, false, 1) X(8, 4, 2, 0, false, 1) X(4, 4, 2, 0, true, 1)
+  X(4, 4, 2, 0, true, 0) X(4, 4, 2, 0, false, 1) X(8, 4, 2, 0, false, 1) X(4, 4, 2, 0, true, 1)   \
+  X(4, 4, 2, 2, true, 0)
 #define TRIOSEQ_MODES(X, r, c, w, k, p, x) X(r, c, w, 1, k, p, x) X(r, c, w, 2, k, p, x) X(r, c, w, 3, k, p, x)
 
 }  // namespace

@@ -227,12 +227,14 @@ __global__ void __launch_bounds__(256) k_gather(const uint32_t* __restrict__ in,
   out[w] = v;
 }
 
-// Meet: one wave folds the chunks' best values of box 0 into the score.
+// Meet: one wave folds the chunks' best values of box 0 (and the halves' own
+// bests, when given) into the score.
 __global__ void __launch_bounds__(64) k_meet_final(const SplitDesc* __restrict__ box,
                                                    const int* __restrict__ partial,
-                                                   const int* __restrict__ err, int32_t* out) {
+                                                   const int* __restrict__ err, const int* __restrict__ own,
+                                                   int32_t* out) {
   const SplitDesc d = box[0];
-  int best = INT32_MIN;
+  int best = (own && threadIdx.x < 2) ? own[threadIdx.x] : INT32_MIN;
   for (uint32_t c = threadIdx.x; c < d.nchunk; c += 64) best = max(best, partial[2 * (d.chunk0 + c)]);
   for (int m = 32; m >= 1; m >>= 1) best = max(best, __shfl_xor(best, m, 64));
   if (threadIdx.x == 0) {
@@ -252,10 +254,11 @@ hipError_t launch_gather(const uint32_t* in, const GatherDesc* d, uint32_t n, ui
 }
 
 hipError_t launch_meet(const SplitDesc* box, const uint32_t* chunk_box, uint32_t nchunks,
-                       const int* planes, int* partial, const int* err, int32_t* out, hipStream_t s) {
+                       const int* planes, int* partial, const int* err, const int* own, int32_t* out,
+                       hipStream_t s) {
   hipLaunchKernelGGL(k_split_part, dim3(nchunks), dim3(256), 0, s, planes, box, chunk_box, nchunks,
                      partial);
-  hipLaunchKernelGGL(k_meet_final, dim3(1), dim3(64), 0, s, box, partial, err, out);
+  hipLaunchKernelGGL(k_meet_final, dim3(1), dim3(64), 0, s, box, partial, err, own, out);
   return hipGetLastError();
 }
 

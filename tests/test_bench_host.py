@@ -31,9 +31,13 @@ def test_scoring_path():
     one_big, one_small = [seqs(128, 100, 90)], [seqs(127, 100, 90)]
     assert bench.scoring_path(one_big, "global", -1, "0x0") == "halves"
     assert bench.scoring_path(one_big, "global", -1, "4x4") == "halves"
-    # Below the half-split threshold, another kind, a forced engine or tile.
+    assert bench.scoring_path(one_big, "local", -1, "0x0") == "halves"
+    assert bench.scoring_path([seqs(2047, 10, 10)], "local", -1, "0x0") == "halves"
+    assert bench.scoring_path([seqs(2048, 10, 10)], "local", -1, "0x0") == "split"
+    assert bench.scoring_path([seqs(2048, 10, 10)], "global", -1, "0x0") == "halves"
+    # Below the half-split threshold, semi-global, a forced engine or tile.
     assert bench.scoring_path(one_small, "global", -1, "0x0") == "split"
-    assert bench.scoring_path(one_big, "local", -1, "0x0") == "split"
+    assert bench.scoring_path(one_big, "semi-global", -1, "0x0") == "split"
     assert bench.scoring_path(one_big, "global", 1, "0x0") == "split"
     assert bench.scoring_path(one_big, "global", -1, "8x4") == "split"
     two = one_big + one_small

@@ -116,6 +116,60 @@ def test_split_triplets(torch_cuda, name, kind, okind):
         assert int(got[0]) == want, (n, int(got[0]), want, info)
 
 
+def motif_triplet(rng, lens, at):
+    """Unrelated random sequences sharing one conserved stretch, placed in the
+    longest sequence at fraction `at` of its length (0: its start, 1: its end),
+    so that the best local alignment lies in the first half, the second half,
+    or across the middle."""
+    t = [synth.uniform_seq(rng, m) for m in lens]
+    ax = int(np.argmax(lens))
+    m = min(40, *[max(n, 1) for n in lens])
+    motif = synth.uniform_seq(rng, m)
+    for q, n in enumerate(lens):
+        if n < m:
+            continue
+        pos = int(round(at * (n - m))) if q == ax else int(rng.integers(0, n - m + 1))
+        t[q][pos:pos + m] = synth.fix_length(rng, synth.mutate(rng, motif, 0.05), m) if q != ax else motif
+    return tuple(t)
+
+
+def test_lone_local_triplet_half_split(torch_cuda):
+    # A lone local triplet under automatic options is scored by halves: the
+    # best of the two halves' own bests and of the paths crossing the middle
+    # plane. Compared with the classic split engine and the oracle where the
+    # best alignment sits in the first half, in the second, or across the
+    # middle, on unrelated and related triplets, odd lengths, ties for the
+    # longest, empty and length-1 sequences, other scorings and replays.
+    rng = np.random.default_rng(47)
+    sc = ts.scoring(kind=ts.LOCAL)
+    cases = []
+    for n in ((300, 120, 140), (257, 257, 90), (129, 40, 66)):
+        for at in (0.0, 0.5, 1.0):
+            cases.append(motif_triplet(rng, n, at))
+    cases += [tuple(synth.uniform_seq(rng, m) for m in n)
+              for n in ((256, 40, 33), (300, 0, 0), (0, 311, 7), (1, 1, 400), (64, 333, 1))]
+    cases += [synth.mutated_triplet(rng, max(n), 0.1, lens=n) for n in ((290, 290, 290), (513, 200, 150))]
+    for q, t in enumerate(cases):
+        n = tuple(int(s.size) for s in t)
+        want = oracle.score(t, kind=oracle.LOCAL)
+        say(f"local half split #{q} lens={n}")
+        got_half, info = run_plan(torch_cuda, [t], sc)
+        got_classic, _ = run_plan(torch_cuda, [t], sc, engine=1)
+        assert int(got_half[0]) == int(got_classic[0]) == want, (q, n, int(got_half[0]), int(got_classic[0]), want)
+        assert ts.score(t, sc) == want
+    for trial in range(3):
+        sub = pins.random_symmetric_sub(rng, -4, 5)
+        gap = int(rng.integers(-5, 1))
+        t = motif_triplet(rng, (200, 150, 170), float(rng.uniform(0, 1)))
+        say(f"local half split scoring trial {trial} gap={gap}")
+        got, _ = run_plan(torch_cuda, [t], ts.scoring(sub=sub, gap=gap, kind=ts.LOCAL))
+        assert int(got[0]) == oracle.score(t, sub, gap, kind=oracle.LOCAL)
+    t = motif_triplet(rng, (400, 380, 390), 0.9)
+    say("local half split graph replays")
+    outs, _ = run_plan(torch_cuda, [t], sc, use_graph=True, reps=4)
+    assert all(int(o[0]) == oracle.score(t, kind=oracle.LOCAL) for o in outs)
+
+
 @pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
 def test_mixed_batch_and_few_wavefronts(torch_cuda, name, kind, okind):
     # One large triplet is split (its panels fold their bests), the rest are
