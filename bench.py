@@ -51,12 +51,12 @@ WORKLOADS = ("single_1k", "single_128", "batch_8192", "single_4k", "served", "tr
 # tile, and a lone global or local triplet under automatic options is scored by
 # halves.
 TRAFFIC = {
-    ("batch_8192_len100-400", "global", "4x4", "batch-packed+lds-direct"): (4.8537e10, "59f5c7ff675def0d"),
-    ("batch_8192_len100-400", "local", "4x4", "batch-packed"): (4.8458e10, "59f5c7ff675def0d"),
-    ("batch_8192_len100-400", "semi-global", "4x4", "batch-packed"): (4.8551e10, "59f5c7ff675def0d"),
-    ("single_1024x1000x1048", "global", "4x4", "halves"): (1.5221e9, "59f5c7ff675def0d"),
-    ("single_4096x4000x4150", "global", "4x4", "halves"): (7.7787e10, "59f5c7ff675def0d"),
-    ("single_128x128x128", "global", "4x4", "halves"): (5.9224e6, "59f5c7ff675def0d"),
+    ("batch_8192_len100-400", "global", "4x4", "batch-packed+lds-direct"): (4.8549e10, "121dba023671257b"),
+    ("batch_8192_len100-400", "local", "4x4", "batch-packed"): (4.8426e10, "121dba023671257b"),
+    ("batch_8192_len100-400", "semi-global", "4x4", "batch-packed"): (4.8503e10, "121dba023671257b"),
+    ("single_1024x1000x1048", "global", "4x4", "halves"): (1.5218e9, "121dba023671257b"),
+    ("single_4096x4000x4150", "global", "4x4", "halves"): (7.7745e10, "121dba023671257b"),
+    ("single_128x128x128", "global", "4x4", "halves"): (5.9148e6, "121dba023671257b"),
     ("single_1024x1000x1048", "local", "4x4", "halves"): (1.6290e9, "121dba023671257b"),
     ("batch_8192_len100-400", "global", "8x4", "batch"): (7.2410e10, "5b986628d09c52c4"),
     ("single_1024x1000x1048", "global", "4x4", "split"): (1.5689e9, "5b986628d09c52c4"),
