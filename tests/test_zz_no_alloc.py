@@ -4,8 +4,8 @@ trioseq_score_batch_packed_noalloc carves every device buffer from the
 library's fixed scratch array. Its scores must equal those of
 trioseq_score_batch_packed on the same device inputs (integers: equality),
 on two calls in a row, the second with a smaller input, for a batch of whole
-triplets, a batch holding split triplets, a lone triplet (scored by halves)
-and the semi-global and local kinds; inputs beyond the scratch limits are
+triplets, a batch holding split triplets, a lone global or local triplet
+(scored by halves) and the semi-global and local kinds; inputs beyond the scratch limits are
 rejected before anything is launched.
 """
 import sys
@@ -85,18 +85,24 @@ def test_batches_twice_second_smaller(torch_cuda, kind):
     assert got[:8].tolist() == want
 
 
-def test_lone_triplets_twice_second_smaller(torch_cuda):
-    # A lone global triplet is scored by halves (gather, two plane sweeps,
-    # the meeting reduction); then a smaller lone triplet, then the empty
-    # and one-residue shapes.
+@pytest.mark.parametrize("kind", [ts.GLOBAL, ts.LOCAL])
+def test_lone_triplets_twice_second_smaller(torch_cuda, kind):
+    # A lone global or local triplet is scored by halves (gather, two plane
+    # sweeps, the meeting reduction; local scoring also folds the halves' own
+    # bests); then a smaller lone triplet, then the empty and one-residue
+    # shapes.
+    sc = ts.scoring(kind=kind)
+    okind = {ts.GLOBAL: oracle.GLOBAL, ts.LOCAL: oracle.LOCAL}[kind]
     rng = synth.rng_for(54)
     big = synth.mutated_triplet(rng, 300, 0.05, lens=(300, 288, 310))
     small = synth.mutated_triplet(rng, 70, 0.05, lens=(70, 64, 77))
     for trips in ([big], [small], [(small[0], small[1][:0], small[2])], [(small[0][:1],) * 3]):
-        say(f"noalloc lone lens={[s.size for s in trips[0]]}")
-        ref, got = both(torch_cuda, trips)
+        say(f"noalloc lone kind={kind} lens={[s.size for s in trips[0]]}")
+        ref, got = both(torch_cuda, trips, sc)
         assert got.tolist() == ref.tolist()
-    assert got.tolist() == [oracle.score(trips[0])]
+        if trips[0][0].size == 300:
+            assert got.tolist() == [oracle.score(trips[0], kind=okind)]
+    assert got.tolist() == [oracle.score(trips[0], kind=okind)]
 
 
 def test_beyond_the_scratch_is_rejected(torch_cuda):
