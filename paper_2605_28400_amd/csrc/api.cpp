@@ -13,6 +13,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -340,19 +341,27 @@ void trioseq_set_wait_limit(uint64_t ns) {
 
 trioseq_status trioseq_pack(const char* seq, uint32_t len, uint32_t* words) {
   if (len && (!seq || !words)) return fail(TRIOSEQ_ERR_INVALID_ARG, "pack: NULL pointer");
-  const uint32_t nw = (len + 15) / 16;
-  for (uint32_t w = 0; w < nw; ++w) {
+  const uint8_t* in = (const uint8_t*)seq;
+  // Validate first (codes of A, C, G, T are 0..3, anything else has a
+  // higher bit set), so an error leaves the words untouched.
+  uint32_t bad = 0;
+  for (uint32_t p = 0; p < len; ++p) bad |= g_code[in[p]];
+  if (bad > 3) {
+    uint32_t p = 0;
+    while (g_code[in[p]] <= 3) ++p;
+    return fail(TRIOSEQ_ERR_BAD_RESIDUE, "pack: character at position " + std::to_string(p) + " is not ACGT");
+  }
+  const uint32_t full = len / 16;
+  for (uint32_t w = 0; w < full; ++w) {
+    const uint8_t* r = in + 16 * (size_t)w;
     uint32_t v = 0;
-    const uint32_t base = w * 16;
-    const uint32_t m = std::min<uint32_t>(16, len - base);
-    for (uint32_t q = 0; q < m; ++q) {
-      const uint8_t c = g_code[(uint8_t)seq[base + q]];
-      if (c > 3)
-        return fail(TRIOSEQ_ERR_BAD_RESIDUE,
-                    "pack: character at position " + std::to_string(base + q) + " is not ACGT");
-      v |= (uint32_t)c << (2 * q);
-    }
+    for (int q = 0; q < 16; ++q) v |= (uint32_t)g_code[r[q]] << (2 * q);
     words[w] = v;
+  }
+  if (len % 16) {
+    uint32_t v = 0;
+    for (uint32_t q = 0; q < len % 16; ++q) v |= (uint32_t)g_code[in[16 * (size_t)full + q]] << (2 * q);
+    words[full] = v;
   }
   return TRIOSEQ_OK;
 }
@@ -1206,6 +1215,11 @@ trioseq_status trioseq_plan_destroy(trioseq_plan* p) {
   return TRIOSEQ_OK;
 }
 
+// Host packing threads: batches of at least kPackParallelMin residues are
+// split over up to kPackThreadsMax threads (the calling one included).
+constexpr uint64_t kPackParallelMin = 1u << 20;
+constexpr size_t kPackThreadsMax = 16;
+
 // Validates and packs host ASCII triplets into one word array.
 static trioseq_status pack_triplets(const trioseq_triplet* t, size_t n, std::vector<uint32_t>* lens,
                                     std::vector<uint64_t>* offs, std::vector<uint32_t>* words) {
@@ -1222,13 +1236,56 @@ static trioseq_status pack_triplets(const trioseq_triplet* t, size_t n, std::vec
   uint64_t total = 0;
   trioseq_packed_layout(lens->data(), n, offs->data(), &total);
   words->assign(std::max<uint64_t>(total, 1), 0u);
-  for (size_t q = 0; q < n; ++q)
-    for (int s = 0; s < 3; ++s) {
-      trioseq_status st = trioseq_pack(t[q].seq[s], t[q].len[s], words->data() + (*offs)[3 * q + s]);
-      if (st != TRIOSEQ_OK)
-        return fail(st, "triplet " + std::to_string(q) + ", sequence " + std::to_string(s) + ": " +
-                            g_err);
+  // Large batches are packed by several host threads, each over a run of
+  // whole triplets of about equal residue count. Each records its first bad
+  // sequence; the first over all is packed again here for its message
+  // (messages are per thread).
+  const uint64_t residues = 16 * total;
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t nthreads = residues < kPackParallelMin ? 1 : std::min<size_t>({hw, kPackThreadsMax, n});
+  std::vector<size_t> first_bad(nthreads, SIZE_MAX);
+  auto pack_range = [&](size_t th, size_t q0, size_t q1) {
+    for (size_t q = q0; q < q1; ++q)
+      for (int s = 0; s < 3; ++s) {
+        bool ok = false;
+        try {  // nothing may leave a worker thread
+          ok = trioseq_pack(t[q].seq[s], t[q].len[s], words->data() + (*offs)[3 * q + s]) == TRIOSEQ_OK;
+        } catch (...) {
+        }
+        if (!ok) {
+          first_bad[th] = 3 * q + s;
+          return;
+        }
+      }
+  };
+  std::vector<std::thread> pool;
+  size_t q0 = 0;
+  for (size_t th = 0; th < nthreads; ++th) {
+    // Triplets that start before the (th+1)-th share of the words; the last
+    // range runs on this thread, and so does any range whose thread could
+    // not be started.
+    const uint64_t goal = total * (th + 1) / nthreads;
+    size_t q1 = q0;
+    while (q1 < n && (th + 1 == nthreads || (*offs)[3 * q1] < goal)) ++q1;
+    bool started = false;
+    if (th + 1 < nthreads) {
+      try {
+        pool.emplace_back(pack_range, th, q0, q1);
+        started = true;
+      } catch (...) {
+      }
     }
+    if (!started) pack_range(th, q0, q1);
+    q0 = q1;
+  }
+  for (std::thread& th : pool) th.join();
+  const size_t bad = *std::min_element(first_bad.begin(), first_bad.end());
+  if (bad != SIZE_MAX) {
+    const size_t q = bad / 3;
+    const int s = (int)(bad % 3);
+    const trioseq_status st = trioseq_pack(t[q].seq[s], t[q].len[s], words->data() + (*offs)[bad]);
+    return fail(st, "triplet " + std::to_string(q) + ", sequence " + std::to_string(s) + ": " + g_err);
+  }
   return TRIOSEQ_OK;
 }
 

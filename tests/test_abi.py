@@ -62,6 +62,38 @@ def test_bad_residue_rejected():
                                             [("A", "C", "G"), ("A", "-", "G")]).value)
 
 
+def test_pack_error_leaves_words_untouched():
+    L = ts.lib()
+    words = (ctypes.c_uint32 * 3)(7, 8, 9)
+    seq = b"ACGT" * 8 + b"ACGN"
+    assert L.trioseq_pack(seq, len(seq), words) == -2
+    assert list(words) == [7, 8, 9]
+    assert b"position 35" in L.trioseq_last_error()
+    ok = b"TGCA" * 9
+    assert L.trioseq_pack(ok, len(ok), words) == 0
+    assert list(words) == [int(w) for w in ts.pack(ok.decode())]
+
+
+def test_large_batch_validation_names_the_first_bad_triplet():
+    # Large enough to be packed by several host threads: the message still
+    # names the first bad triplet and sequence in batch order, and nothing
+    # is written to the scores.
+    rng = np.random.default_rng(3)
+    acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
+    trips = [[acgt[rng.integers(0, 4, 150)].tobytes() for _ in range(3)] for _ in range(3000)]
+    trips[2999][0] = b"N" + trips[2999][0][1:]
+    trips[1700][2] = trips[1700][2][:-1] + b"x"
+    trips[2200][1] = b"-" + trips[2200][1][1:]
+    arr, keep = ts.triplet_array([tuple(t) for t in trips])
+    out = np.full(len(trips), 5, dtype=np.int32)
+    L = ts.lib()
+    r = L.trioseq_score_batch(arr, len(trips), ctypes.byref(ts.scoring()),
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None)
+    assert r == -2
+    assert L.trioseq_last_error() == b"triplet 1700, sequence 2: pack: character at position 149 is not ACGT"
+    assert (out == 5).all()
+
+
 def test_asymmetric_matrix_rejected():
     sub = np.full((4, 4), -1)
     np.fill_diagonal(sub, 1)
