@@ -744,32 +744,9 @@ trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested
 
 }  // namespace trioseq
 
-// Half-split scoring of a lone global triplet. Its longest sequence S_a is
-// cut at mid; the first half (S_a[0, mid), S_r, S_c) is swept forward and the
-// second half reversed (rev S_a[mid, n_a), rev S_r, rev S_c), concurrently,
-// both writing their last slice, a plane over (S_r, S_c). Every alignment
-// crosses the slice a = mid, so the score is the best F[p][q] + R[P-p][Q-q]
-// over that plane (the crossing identity Hirschberg's method rests on). Each
-// half's pipeline of panels is as long as the whole triplet's but sweeps half
-// the slices, and the two fill together: the lone triplet finishes sooner.
-// A local alignment either crosses the plane (the same identity, over the
-// halves' local values) or lies within one half, so its score is the best of
-// that plane maximum and the two halves' own bests. Local scoring does more
-// work per cell, so the panel grid is busy enough on its own sooner: by
-// default it takes the halves only below kHalfSplitMaxLocal residues (a
-// threshold the caller sets lifts that cap).
-constexpr uint32_t kHalfSplitMin = 128;        // shortest longest-sequence for it
-constexpr uint32_t kHalfSplitMaxLocal = 2048;  // local scoring, default threshold
-struct HalfSplit {
-  uint32_t lens[6];
-  uint64_t offs[6];      // word offsets in the gathered buffer
-  GatherDesc gather[6];
-  uint32_t words = 0;    // gathered words
-  uint32_t rows = 0, cols = 0;
-};
+namespace trioseq {
 
-static bool half_split_layout(const uint32_t* lens, const uint64_t* word_off, int32_t min_len,
-                              HalfSplit* h) {
+bool half_split_layout(const uint32_t* lens, const uint64_t* word_off, int32_t min_len, HalfSplit* h) {
   int ax = 0;
   for (int q = 1; q < 3; ++q)
     if (lens[q] > lens[ax]) ax = q;
@@ -805,6 +782,19 @@ static bool half_split_layout(const uint32_t* lens, const uint64_t* word_off, in
   return true;
 }
 
+bool half_split_choice(const uint32_t* lens, const uint64_t* word_off, size_t n, int kind,
+                       const trioseq_plan_options& o, HalfSplit* h) {
+  if (n != 1 || o.lane_exchange == 2) return false;
+  if (kind == kLocal) {
+    if (o.half_split_min == 0 && std::max({lens[0], lens[1], lens[2]}) >= kHalfSplitMaxLocal) return false;
+  } else if (kind != kGlobal) {
+    return false;
+  }
+  return half_split_layout(lens, word_off, o.half_split_min, h);
+}
+
+}  // namespace trioseq
+
 static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* word_off, size_t n,
                                        const trioseq_scoring* scp, const trioseq_plan_options* opts,
                                        trioseq_plan** out, const PlanMemory* mem = nullptr) {
@@ -829,11 +819,7 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
   // halves (local: the best of the two halves' own bests and of the paths
   // that cross the middle plane).
   HalfSplit hs;
-  const bool half_kind =
-      scp->kind == kGlobal ||
-      (scp->kind == kLocal && o.lane_exchange != 2 &&
-       (o.half_split_min != 0 || n != 1 || std::max({lens[0], lens[1], lens[2]}) < kHalfSplitMaxLocal));
-  const bool half = n == 1 && defaults && half_kind && half_split_layout(lens, word_off, o.half_split_min, &hs);
+  const bool half = defaults && half_split_choice(lens, word_off, n, scp->kind, o, &hs);
   const trioseq_plan_options ho{-1, 4, 4, 0, 0, 2, o.panel_group, o.lane_exchange};  // the plane kernels' shape
   DeviceProps dp;
   st = device_props(&dp);

@@ -144,6 +144,40 @@ trioseq_status score_packed_in_region(const uint32_t* d_words, const uint64_t* d
 // a run needs more), so the levels of an alignment allocate almost nothing;
 // the generation word is shared by the runs, so face tags of an earlier run
 // never look current. Not thread-safe; runs are stream-ordered on `s`.
+// Half-split scoring of a lone triplet by a plan. Its longest sequence S_a is
+// cut at mid; the first half (S_a[0, mid), S_r, S_c) is swept forward and the
+// second half reversed (rev S_a[mid, n_a), rev S_r, rev S_c), concurrently,
+// both writing their last slice, a plane over (S_r, S_c). Every alignment
+// crosses the slice a = mid, so the score is the best F[p][q] + R[P-p][Q-q]
+// over that plane (the crossing identity Hirschberg's method rests on). Each
+// half's pipeline of panels is as long as the whole triplet's but sweeps half
+// the slices, and the two fill together: the lone triplet finishes sooner.
+// A local alignment either crosses the plane (the same identity, over the
+// halves' local values) or lies within one half, so its score is the best of
+// that plane maximum and the two halves' own bests. Local scoring does more
+// work per cell, so the panel grid is busy enough on its own sooner: by
+// default it takes the halves only below kHalfSplitMaxLocal residues (a
+// threshold the caller sets lifts that cap).
+constexpr uint32_t kHalfSplitMin = 128;        // shortest longest-sequence for it
+constexpr uint32_t kHalfSplitMaxLocal = 2048;  // local scoring, default threshold
+struct HalfSplit {
+  uint32_t lens[6];
+  uint64_t offs[6];      // word offsets in the gathered buffer
+  GatherDesc gather[6];
+  uint32_t words = 0;    // gathered words
+  uint32_t rows = 0, cols = 0;
+};
+
+// Lays out the halves (gathered sequences, axes, plane size) of a triplet
+// whose longest sequence has at least min_len residues (0: kHalfSplitMin;
+// -1: never); false if it has not.
+bool half_split_layout(const uint32_t* lens, const uint64_t* word_off, int32_t min_len, HalfSplit* h);
+// Whether n triplets of this kind, under these options, are one triplet
+// scored by halves (global, or local below kHalfSplitMaxLocal unless the
+// options set a threshold; the plane kernels' lane exchange), and its layout.
+bool half_split_choice(const uint32_t* lens, const uint64_t* word_off, size_t n, int kind,
+                       const trioseq_plan_options& o, HalfSplit* h);
+
 struct PlaneWorkspace {
   struct Buf {
     void* p = nullptr;

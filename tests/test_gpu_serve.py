@@ -199,6 +199,40 @@ def test_served_long_requests_equal_oracle(gpu):
             assert ts.score(t) == got[q]
 
 
+@pytest.mark.parametrize("kind,okind", [(ts.GLOBAL, oracle.GLOBAL), (ts.LOCAL, oracle.LOCAL),
+                                        (ts.SEMI_GLOBAL, oracle.SEMI_GLOBAL)],
+                         ids=["global", "local", "semi-global"])
+def test_rounds_of_one_request(gpu, kind, okind):
+    # Each request waited for (and its round given time to end) before the
+    # next is submitted, so every round holds one request and runs alone:
+    # lone requests split into panel jobs over the whole device, for each
+    # kind. Odd lengths, the longest on each axis, an empty sequence, and
+    # local alignments at either end of the longest sequence.
+    rng = synth.rng_for(37)
+    reqs = [synth.mutated_triplet(rng, max(n), 0.08, lens=n)
+            for n in ((300, 280, 290), (129, 200, 77), (90, 60, 257), (500, 0, 310), (127, 100, 90))]
+    for at in (0.0, 1.0):
+        t = [synth.uniform_seq(rng, n) for n in (400, 150, 170)]
+        motif = synth.uniform_seq(rng, 40)
+        t[0][int(at * 360):int(at * 360) + 40] = motif
+        t[1][50:90] = motif
+        t[2][60:100] = motif
+        reqs.append(tuple(t))
+    want = [oracle.score(t, kind=okind) for t in reqs]
+    srv = ts.Server(max_len=512, sc=ts.scoring(kind=kind), max_device_bytes=4 << 30)
+    got = []
+    for q, t in enumerate(reqs):
+        say(f"round of one request #{q} kind={kind} lens={[s.size for s in t]}")
+        r = srv.wait(srv.submit(t), timeout_s=60)
+        assert r["status"] == 0, r
+        got.append(r["score"])
+        time.sleep(0.01)
+    st = srv.stats()
+    srv.close()
+    assert got == want, [(q, got[q], want[q]) for q in range(len(reqs)) if got[q] != want[q]]
+    assert st["rounds"] == len(reqs)
+
+
 @pytest.mark.parametrize("inflight", [1, 8])
 def test_rounds_in_flight_setting(gpu, inflight):
     reqs = mixed_requests(35, 160, lo=8, hi=200)
