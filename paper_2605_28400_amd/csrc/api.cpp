@@ -261,7 +261,7 @@ struct trioseq_plan {
   TripletDesc* d_desc = nullptr;
   JobDesc* d_jobs = nullptr;
   int* d_counter = nullptr;  // job queue head
-  int* d_ctl = nullptr;      // [0] generation, [1] error flag
+  int* d_ctl = nullptr;      // [0] generation, [1] error flag, [2] meeting counter (0 between runs)
   int* d_face = nullptr;     // per-wave workspace of whole-triplet jobs
   uint64_t face_stride = 0;
   int* d_pface = nullptr;    // panel-face pool of split triplets
@@ -277,8 +277,7 @@ struct trioseq_plan {
   int* d_plane = nullptr;           // the two last-slice planes
   uint64_t* d_plane_off = nullptr;  // {0, plane ints}
   SplitDesc* d_sdesc = nullptr;     // the meeting box
-  uint32_t* d_chunk_box = nullptr;  // all 0 (one box)
-  int* d_partial = nullptr;         // per chunk: best, index
+  int* d_partial = nullptr;         // per chunk: its best
   int32_t* d_hscores = nullptr;     // the halves' own scores (unused)
   // graph replay
   bool use_graph = false;
@@ -316,7 +315,7 @@ static void plan_free(trioseq_plan* p) {
   (void)hipFree(p->d_red);
   (void)hipFree(p->d_pkbnd);
   for (void* q : {(void*)p->d_hwords, (void*)p->d_gather, (void*)p->d_plane, (void*)p->d_plane_off,
-                  (void*)p->d_sdesc, (void*)p->d_chunk_box, (void*)p->d_partial, (void*)p->d_hscores})
+                  (void*)p->d_sdesc, (void*)p->d_partial, (void*)p->d_hscores})
     (void)hipFree(q);
   delete p;
 }
@@ -968,17 +967,15 @@ static trioseq_status plan_create_impl(const uint32_t* lens, const uint64_t* wor
         (e = dalloc((void**)&p->d_plane, 2 * pints * 4)) != hipSuccess ||
         (e = dalloc((void**)&p->d_plane_off, sizeof plane_off)) != hipSuccess ||
         (e = dalloc((void**)&p->d_sdesc, sizeof box)) != hipSuccess ||
-        (e = dalloc((void**)&p->d_chunk_box, p->h_nchunk * 4)) != hipSuccess ||
-        (e = dalloc((void**)&p->d_partial, p->h_nchunk * 8)) != hipSuccess ||
+        (e = dalloc((void**)&p->d_partial, p->h_nchunk * 4)) != hipSuccess ||
         (e = dalloc((void**)&p->d_hscores, 8)) != hipSuccess)
       return region_fail(e, "half-split buffers");
     if ((e = hipMemcpyAsync(p->d_gather, hs.gather, sizeof hs.gather, hipMemcpyHostToDevice, is)) != hipSuccess ||
         (e = hipMemcpyAsync(p->d_plane_off, plane_off, sizeof plane_off, hipMemcpyHostToDevice, is)) !=
             hipSuccess ||
-        (e = hipMemcpyAsync(p->d_sdesc, &box, sizeof box, hipMemcpyHostToDevice, is)) != hipSuccess ||
-        (e = hipMemsetAsync(p->d_chunk_box, 0, p->h_nchunk * 4, is)) != hipSuccess)
+        (e = hipMemcpyAsync(p->d_sdesc, &box, sizeof box, hipMemcpyHostToDevice, is)) != hipSuccess)
       return hip_bail(e, "half-split buffers");
-    p->workspace_bytes += 2 * pints * 4 + (uint64_t)hs.words * 4 + p->h_nchunk * 12 + 256;
+    p->workspace_bytes += 2 * pints * 4 + (uint64_t)hs.words * 4 + p->h_nchunk * 4 + 256;
     // The host sources of these copies live until this function returns.
     if ((e = hipStreamSynchronize(is)) != hipSuccess) return hip_bail(e, "plan init");
   }
@@ -1135,8 +1132,8 @@ static hipError_t plan_enqueue(trioseq_plan* p, const uint32_t* d_words, int32_t
     a.plane = p->d_plane;
     a.plane_off = p->d_plane_off;
     if ((e = launch_sweep(p->ks, p->modes, a, p->grid, s)) != hipSuccess) return e;
-    return launch_meet(p->d_sdesc, p->d_chunk_box, p->h_nchunk, p->d_plane, p->d_partial, p->d_ctl + 1,
-                       p->sc.kind == kLocal ? p->d_hscores : nullptr, d_scores, s);
+    return launch_meet(p->d_sdesc, p->h_nchunk, p->d_plane, p->d_partial, p->d_ctl + 1,
+                       p->sc.kind == kLocal ? p->d_hscores : nullptr, p->d_ctl + 2, d_scores, s);
   }
   if ((e = launch_prepare(p->d_ctl, p->d_counter, p->d_red, p->red_pairs, s)) != hipSuccess)
     return e;

@@ -120,7 +120,8 @@ trioseq_status layout_grid(const Layout& L, const DeviceProps& dp, int requested
 // allocation-free entry point). plain: any data, carved in order; pool: only
 // ever (value, tag) face pairs at even int offsets from its fixed base, or the
 // zeros it started with, so a tag slot never holds a value; ctl (generation
-// word, error flag) and counter (queue head) persist from call to call, and
+// word, error flag, half-split meeting counter, at least 3 ints, zeroed
+// before first use) and counter (queue head) persist from call to call, and
 // the generation only grows, so no stale tag ever looks current. stream:
 // where the plan's initialisation runs (the caller's).
 struct PlanMemory {

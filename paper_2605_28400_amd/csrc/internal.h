@@ -200,13 +200,13 @@ struct GatherDesc {
 };
 hipError_t launch_gather(const uint32_t* in, const GatherDesc* d, uint32_t n, uint32_t words_out,
                          uint32_t* out, int* ctl, int* counter, hipStream_t s);
-// After launch_split's first stage over one box: out[0] = the best F + R of
-// box 0, or INT32_MIN if err[0] is set (a wait of the run gave up). With
-// own non-null (local scoring), the best also covers own[0] and own[1], the
-// halves' own bests.
-hipError_t launch_meet(const SplitDesc* box, const uint32_t* chunk_box, uint32_t nchunks,
-                       const int* planes, int* partial, const int* err, const int* own, int32_t* out,
-                       hipStream_t s);
+// out[0] = the best F + R over box 0 of planes (its nchunks chunks of
+// kSplitChunk cells, numbered from 0), or INT32_MIN if err[0] is set (a wait
+// of the run gave up). With own non-null (local scoring), the best also
+// covers own[0] and own[1], the halves' own bests. partial: nchunks ints of
+// scratch; counter: one int that is 0 before the call and is left 0.
+hipError_t launch_meet(const SplitDesc* box, uint32_t nchunks, const int* planes, int* partial,
+                       const int* err, const int* own, int* counter, int32_t* out, hipStream_t s);
 // out[3b] = best F + R of box b, out[3b+1], out[3b+2] = its (p, q).
 // chunk_box[c] = the box of chunk c; partial: 2 ints per chunk.
 hipError_t launch_split(const int* planes, const SplitDesc* boxes, uint32_t n, const uint32_t* chunk_box,

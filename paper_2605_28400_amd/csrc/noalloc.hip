@@ -9,9 +9,10 @@
 // handed to kernels and copies.
 //
 // Layout of the array: [control 4 KiB | panel-face pool | plain data].
-//  * control: the run generation and error flag (ctl[0], ctl[1]) and the job
-//    queue head; they persist from call to call and the generation only
-//    grows, so a face tag written by an earlier call never looks current;
+//  * control: the run generation and error flag (ctl[0], ctl[1]), the
+//    half-split meeting counter (ctl[2], 0 between calls) and the job queue
+//    head; they persist from call to call and the generation only grows, so
+//    a face tag written by an earlier call never looks current;
 //  * pool: only ever (value, tag) pairs of split triplets' faces, at even
 //    offsets from this fixed base (or the zeros it started with), so a tag
 //    slot never holds a plain value;

@@ -227,19 +227,63 @@ __global__ void __launch_bounds__(256) k_gather(const uint32_t* __restrict__ in,
   out[w] = v;
 }
 
-// Meet: one wave folds the chunks' best values of box 0 (and the halves' own
-// bests, when given) into the score.
-__global__ void __launch_bounds__(64) k_meet_final(const SplitDesc* __restrict__ box,
-                                                   const int* __restrict__ partial,
-                                                   const int* __restrict__ err, const int* __restrict__ own,
-                                                   int32_t* out) {
+// Meet, in one launch: workgroup c reduces chunk c of box 0 (kSplitChunk
+// plane cells) to its best F + R; the workgroup that finishes last folds the
+// chunks' bests, and the halves' own bests when given, into the score
+// (INT32_MIN if a wait of the run gave up) and clears the counter for the
+// next run.
+__global__ void __launch_bounds__(256) k_meet(const int* __restrict__ planes, const SplitDesc* __restrict__ box,
+                                              uint32_t nchunks, int* partial, const int* __restrict__ err,
+                                              const int* __restrict__ own, int* counter, int32_t* out) {
+  __shared__ int s_val[256];
+  __shared__ int s_last;
   const SplitDesc d = box[0];
-  int best = (own && threadIdx.x < 2) ? own[threadIdx.x] : INT32_MIN;
-  for (uint32_t c = threadIdx.x; c < d.nchunk; c += 64) best = max(best, partial[2 * (d.chunk0 + c)]);
-  for (int m = 32; m >= 1; m >>= 1) best = max(best, __shfl_xor(best, m, 64));
+  const int* F = planes + d.fwd;
+  const int* R = planes + d.bwd;
+  const uint32_t cells = d.rows * d.cols;
+  const uint32_t lo = blockIdx.x * kSplitChunk;
+  const uint32_t hi = min(cells, lo + kSplitChunk);
+  int best = INT32_MIN;
+  // kSplitBatch cells per thread per pass, their loads issued together.
+  for (uint32_t q0 = lo + threadIdx.x; q0 < hi; q0 += kSplitBatch * blockDim.x) {
+    int v[kSplitBatch];
+#pragma unroll
+    for (int u = 0; u < kSplitBatch; ++u) {
+      const uint32_t q = q0 + u * blockDim.x, qc = min(q, hi - 1);
+      const uint32_t p = qc / d.cols, c = qc - p * d.cols;
+      const int sv = F[qc] + R[(d.rows - 1 - p) * d.cols + (d.cols - 1 - c)];
+      v[u] = q < hi ? sv : INT32_MIN;
+    }
+#pragma unroll
+    for (int u = 0; u < kSplitBatch; ++u) best = max(best, v[u]);
+  }
+  s_val[threadIdx.x] = best;
+  __syncthreads();
+  for (uint32_t w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s_val[threadIdx.x] = max(s_val[threadIdx.x], s_val[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&partial[blockIdx.x], s_val[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int done = __hip_atomic_fetch_add(counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = done == (int)nchunks - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  int b = (own && threadIdx.x < 2) ? own[threadIdx.x] : INT32_MIN;
+  for (uint32_t c = threadIdx.x; c < nchunks; c += blockDim.x)
+    b = max(b, __hip_atomic_load(&partial[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  __syncthreads();
+  s_val[threadIdx.x] = b;
+  __syncthreads();
+  for (uint32_t w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s_val[threadIdx.x] = max(s_val[threadIdx.x], s_val[threadIdx.x + w]);
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
     const bool bad = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-    __hip_atomic_store(out, bad ? INT32_MIN : best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(out, bad ? INT32_MIN : s_val[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(counter, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -253,12 +297,11 @@ hipError_t launch_gather(const uint32_t* in, const GatherDesc* d, uint32_t n, ui
   return hipGetLastError();
 }
 
-hipError_t launch_meet(const SplitDesc* box, const uint32_t* chunk_box, uint32_t nchunks,
-                       const int* planes, int* partial, const int* err, const int* own, int32_t* out,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_split_part, dim3(nchunks), dim3(256), 0, s, planes, box, chunk_box, nchunks,
-                     partial);
-  hipLaunchKernelGGL(k_meet_final, dim3(1), dim3(64), 0, s, box, partial, err, own, out);
+hipError_t launch_meet(const SplitDesc* box, uint32_t nchunks, const int* planes, int* partial,
+                       const int* err, const int* own, int* counter, int32_t* out, hipStream_t s) {
+  if (nchunks == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_meet, dim3(nchunks), dim3(256), 0, s, planes, box, nchunks, partial, err, own, counter,
+                     out);
   return hipGetLastError();
 }
 
