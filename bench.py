@@ -54,10 +54,10 @@ TRAFFIC = {
     ("batch_8192_len100-400", "global", "4x4", "batch-packed+lds-direct"): (4.8549e10, "121dba023671257b"),
     ("batch_8192_len100-400", "local", "4x4", "batch-packed"): (4.8426e10, "121dba023671257b"),
     ("batch_8192_len100-400", "semi-global", "4x4", "batch-packed"): (4.8503e10, "121dba023671257b"),
-    ("single_1024x1000x1048", "global", "4x4", "halves"): (1.5218e9, "121dba023671257b"),
+    ("single_1024x1000x1048", "global", "4x4", "halves"): (1.5255e9, "121dba023671257b"),
     ("single_4096x4000x4150", "global", "4x4", "halves"): (7.7745e10, "121dba023671257b"),
-    ("single_128x128x128", "global", "4x4", "halves"): (5.9148e6, "121dba023671257b"),
-    ("single_1024x1000x1048", "local", "4x4", "halves"): (1.6290e9, "121dba023671257b"),
+    ("single_128x128x128", "global", "4x4", "halves"): (5.8941e6, "121dba023671257b"),
+    ("single_1024x1000x1048", "local", "4x4", "halves"): (1.6171e9, "121dba023671257b"),
     ("batch_8192_len100-400", "global", "8x4", "batch"): (7.2410e10, "5b986628d09c52c4"),
     ("single_1024x1000x1048", "global", "4x4", "split"): (1.5689e9, "5b986628d09c52c4"),
     ("single_4096x4000x4150", "global", "4x4", "split"): (7.9174e10, "5b986628d09c52c4"),
