@@ -170,6 +170,30 @@ def test_lone_local_triplet_half_split(torch_cuda):
     assert all(int(o[0]) == oracle.score(t, kind=oracle.LOCAL) for o in outs)
 
 
+def test_which_lone_triplets_take_the_halves(torch_cuda):
+    # The halves path sweeps two triplets (twice the panel jobs of the
+    # classic split, here 2 x 4 against 4): global from 128 residues on, local
+    # from 128 to 2047 (an explicit threshold lifts that cap), semi-global
+    # never. Scores against the oracle either way.
+    rng = np.random.default_rng(49)
+    cases = [(ts.GLOBAL, oracle.GLOBAL, 2048, 0, 8), (ts.LOCAL, oracle.LOCAL, 2047, 0, 8),
+             (ts.LOCAL, oracle.LOCAL, 2048, 0, 4), (ts.LOCAL, oracle.LOCAL, 2048, 128, 8),
+             (ts.SEMI_GLOBAL, oracle.SEMI_GLOBAL, 2047, 0, 4)]
+    for kind, okind, n0, hmin, panels in cases:
+        t = synth.mutated_triplet(rng, n0, 0.1, lens=(n0, 40, 40))
+        lens, off, words = ts.pack_batch([t])
+        plan = ts.Plan(lens, off, sc=ts.scoring(kind=kind), half_split_min=hmin)
+        d_words = torch_cuda.from_numpy(words.view(np.int32)).cuda()
+        d_scores = torch_cuda.full((1,), -7, dtype=torch_cuda.int32, device="cuda")
+        say(f"lone triplet kind={kind} n0={n0} half_split_min={hmin}")
+        plan.run(d_words, d_scores)
+        torch_cuda.cuda.synchronize()
+        info = plan.info()
+        plan.close()
+        assert info["panels"] == panels, (kind, n0, hmin, info)
+        assert int(d_scores.cpu()[0]) == oracle.score(t, kind=okind)
+
+
 @pytest.mark.parametrize("name,kind,okind", KINDS, ids=KIND_IDS)
 def test_mixed_batch_and_few_wavefronts(torch_cuda, name, kind, okind):
     # One large triplet is split (its panels fold their bests), the rest are
