@@ -160,6 +160,10 @@ trioseq_status launch_round(trioseq_server* s, Slot& sl, std::vector<Request>& b
     *err = trioseq_last_error();
     return st;
   }
+  // Rounds of several split requests: their panel jobs are swept by
+  // single-wave workgroups (two computing waves per SIMD) rather than by
+  // computing and staging wave pairs.
+  if (L.modes == 2 && L.desc.size() >= 2) L.modes = 3;
   int grid = 0, wpc = 0;
   st = layout_grid(L, s->dp, 0, &grid, &wpc);
   if (st != TRIOSEQ_OK) {
