@@ -139,8 +139,9 @@ void record_result(trioseq_server* s, const Request& r, int32_t score, int32_t s
 }
 
 // Builds and launches one round in slot `sl` from `batch` (lock not held).
+// alone: no other round is on the device.
 trioseq_status launch_round(trioseq_server* s, Slot& sl, std::vector<Request>& batch, Layout* L_out,
-                            std::string* err) {
+                            std::string* err, bool alone) {
   const size_t n = batch.size();
   std::vector<uint32_t> lens(3 * n);
   std::vector<uint64_t> offs(3 * n);
@@ -160,10 +161,11 @@ trioseq_status launch_round(trioseq_server* s, Slot& sl, std::vector<Request>& b
     *err = trioseq_last_error();
     return st;
   }
-  // Rounds of several split requests: their panel jobs are swept by
-  // single-wave workgroups (two computing waves per SIMD) rather than by
-  // computing and staging wave pairs.
-  if (L.modes == 2 && L.desc.size() >= 2) L.modes = 3;
+  // Rounds of several split requests, or of one that shares the device with
+  // other rounds: their panel jobs are swept by single-wave workgroups (two
+  // computing waves per SIMD) rather than by computing and staging wave
+  // pairs.
+  if (L.modes == 2 && (L.desc.size() >= 2 || !alone)) L.modes = 3;
   int grid = 0, wpc = 0;
   st = layout_grid(L, s->dp, 0, &grid, &wpc);
   if (st != TRIOSEQ_OK) {
@@ -278,7 +280,7 @@ void worker_main(trioseq_server* s) {
       trioseq_status st = TRIOSEQ_ERR_TOO_LARGE;
       std::vector<Request> back;
       while (!batch.empty()) {
-        st = launch_round(s, sl, batch, &L, &err);
+        st = launch_round(s, sl, batch, &L, &err, busy == 0);
         if (st != TRIOSEQ_ERR_TOO_LARGE || batch.size() == 1) break;
         // Does not fit: return the second half to the queue front.
         const size_t keep = batch.size() / 2;
